@@ -1,0 +1,145 @@
+"""Pins for the oracle's phase space, density sampler, cuts and polarisation vectors:
+closed forms (phase-space volumes, RAMBO's one-particle energy spectrum), quadrature
+from scipy, conservation laws and hand-computed events."""
+from math import pi
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+from oracle import cuts, pdf, rambo
+from oracle.helicity import polarisation
+from oracle.recursion import mdot
+from paper_1002_3446_amd import inputs
+
+A, B = -1.3, 5
+
+
+def test_primitive_is_antiderivative():
+    x = np.array([1e-4, 1e-3, 0.01, 0.1, 0.5, 0.9])
+    h = 1e-7 * x
+    d = (pdf.primitive(x + h, A, B) - pdf.primitive(x - h, A, B)) / (2 * h)
+    assert np.allclose(d, pdf.density(x, A, B), rtol=1e-6)
+
+
+@pytest.mark.parametrize("n", [5, 8, 12])
+def test_norm_matches_quadrature(n):
+    tau = pdf.tau_min(n, 20.0, 14000.0)
+    q, _ = integrate.quad(lambda x: pdf.density(x, A, B), tau, 1.0, points=[10 * tau, 100 * tau], limit=200)
+    assert abs(pdf.norm(tau, A, B) / q - 1) < 1e-10
+
+
+def test_sampler_inverts_cdf():
+    tau = pdf.tau_min(8, 20.0, 14000.0)
+    Z = pdf.norm(tau, A, B)
+    u = np.array([1e-9, 1e-3, 0.1, 0.5, 0.9, 0.999, 1 - 1e-9])
+    x = pdf.sample(u, tau, A, B)
+    for ui, xi in zip(u, x):
+        q, _ = integrate.quad(lambda t: pdf.density(t, A, B), tau, xi, limit=200)
+        assert abs(q / Z - ui) < 1e-9 * max(ui, 1e-3)
+    assert np.all((x >= tau) & (x < 1))
+
+
+def test_sampler_distribution():
+    tau = pdf.tau_min(8, 20.0, 14000.0)
+    Z = pdf.norm(tau, A, B)
+    x = pdf.sample(inputs.open_uniforms(11, 20000), tau, A, B)
+    cdf = lambda t: (pdf.primitive(np.clip(t, tau, 1), A, B) - pdf.primitive(tau, A, B)) / Z
+    assert stats.kstest(x, cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("k", [2, 3, 6, 10])
+def test_rambo_conservation_and_masslessness(k):
+    rho = inputs.open_uniforms(4, (500, k, 4))
+    rs = 1000.0
+    p = rambo.rambo(rho, rs)
+    tot = p.sum(1)
+    assert np.allclose(tot[:, 0], rs, rtol=1e-12)
+    assert np.all(np.abs(tot[:, 1:]) < 1e-9 * rs)
+    m2 = p[..., 0] ** 2 - (p[..., 1:] ** 2).sum(-1)
+    assert np.all(np.abs(m2) < 1e-9 * p[..., 0] ** 2 + 1e-18)
+
+
+def test_phase_space_volume_closed_forms():
+    s = 1234.5**2
+    assert abs(rambo.volume(2, s) * 8 * pi - 1) < 1e-14
+    assert abs(rambo.volume(3, s) * 256 * pi**3 / s - 1) < 1e-14
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_rambo_single_particle_spectrum(k):
+    """Flat massless k-body phase space: x = 2E/sqrt(s) has density
+    (k-1)(k-2) x (1-x)^(k-3), and cos(theta) is uniform."""
+    rho = inputs.open_uniforms(8, (40000, k, 4))
+    p = rambo.rambo(rho, 2.0)
+    x = p[:, 0, 0]
+    cdf = lambda t: integrate.quad(lambda y: (k - 1) * (k - 2) * y * (1 - y) ** (k - 3), 0, t)[0]
+    cdfv = np.vectorize(cdf)
+    assert stats.kstest(x[:4000], cdfv).pvalue > 1e-3
+    ct = p[:, 0, 3] / np.linalg.norm(p[:, 0, 1:], axis=1)
+    assert stats.kstest(ct, stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+def test_rambo_two_body_back_to_back():
+    p = rambo.rambo(inputs.open_uniforms(2, (100, 2, 4)), 500.0)
+    assert np.allclose(p[:, 0, 0], 250.0, rtol=1e-12)
+    assert np.allclose(p[:, 0, 1:], -p[:, 1, 1:], atol=1e-9)
+
+
+def test_boost_preserves_masses_and_matches_beams():
+    rho = inputs.open_uniforms(4, (200, 4, 4))
+    x = inputs.x_fractions(4, 200, 1e-3)
+    S = 14000.0
+    s_hat = x[:, 0] * x[:, 1] * S**2
+    p = rambo.boost_z(rambo.rambo(rho, np.sqrt(s_hat)), x[:, 0], x[:, 1])
+    b = rambo.beams(x[:, 0], x[:, 1], S)
+    assert np.allclose(p.sum(1), b.sum(1), rtol=1e-11, atol=1e-8)
+    m2 = p[..., 0] ** 2 - (p[..., 1:] ** 2).sum(-1)
+    assert np.all(np.abs(m2) < 1e-9 * p[..., 0] ** 2)
+
+
+def test_cuts_hand_event():
+    # three jets with known pT, eta, phi
+    def jet(pt, eta, phi):
+        return [pt * np.cosh(eta), pt * np.cos(phi), pt * np.sin(phi), pt * np.sinh(eta)]
+    p = np.array([[jet(30, 0.1, 0.0), jet(25, -1.0, 3.0), jet(50, 2.0, -3.0)]])
+    c = cuts.cuts(p, 20.0, 2.5, 0.4)
+    assert c["pass_"][0]
+    assert np.isclose(c["ht"][0], 105.0)
+    # jets 2 and 3: delta phi wraps to 2 pi - 6, delta eta 3
+    assert np.isclose(c["rmin"][0], min(np.hypot(1.1, 3.0), np.hypot(1.9, 3.0), np.hypot(3.0, 2 * np.pi - 6.0)))
+    for bad in ([jet(19.9, 0, 0), jet(30, 1, 2), jet(30, -1, -2)],
+                [jet(30, 2.6, 0), jet(30, 1, 2), jet(30, -1, -2)],
+                [jet(30, 0.0, 0), jet(30, 0.3, 0.2), jet(30, -1, -2)]):
+        assert not cuts.cuts(np.array([bad]), 20.0, 2.5, 0.4)["pass_"][0]
+
+
+def test_cuts_strict_and_brute_force_rmin():
+    rng = np.random.default_rng(3)
+    pt, eta, phi = rng.uniform(10, 100, (50, 5)), rng.uniform(-3, 3, (50, 5)), rng.uniform(-pi, pi, (50, 5))
+    p = np.stack([pt * np.cosh(eta), pt * np.cos(phi), pt * np.sin(phi), pt * np.sinh(eta)], -1)
+    c = cuts.cuts(p, 20.0, 2.5, 0.4)
+    for e in range(50):
+        best = 1e9
+        for i in range(5):
+            for j in range(i + 1, 5):
+                d = abs(phi[e, i] - phi[e, j])
+                d = min(d, 2 * pi - d)
+                best = min(best, np.hypot(eta[e, i] - eta[e, j], d))
+        assert np.isclose(c["rmin"][e], best, rtol=1e-12)
+
+
+def test_polarisation_properties():
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=(100, 3))
+    E = np.linalg.norm(v, axis=1)
+    p = np.concatenate([E[:, None], v], 1)
+    p = np.concatenate([p, [[2.0, 0, 0, 2.0], [3.0, 0, 0, -3.0]]])
+    for h in (1.0, -1.0):
+        e = polarisation(p, np.full(len(p), h))
+        assert np.all(np.abs(mdot(e, p)) < 1e-14 * p[:, 0])
+        assert np.all(np.abs(mdot(e, e)) < 1e-15)
+        assert np.allclose(mdot(e, np.conj(e)), -1.0, atol=1e-15)
+    ep = polarisation(p, np.ones(len(p)))
+    em = polarisation(p, -np.ones(len(p)))
+    assert np.allclose(mdot(ep, np.conj(em)), 0.0, atol=1e-15)
