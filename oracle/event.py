@@ -2,6 +2,9 @@
 
 generate():  draws (Philox) -> parton fractions -> RAMBO -> boost -> cuts and observables
              -> helicity vectors -> recursion -> |A|^2 -> weight   (Secs. 3 and 4)
+             |A|^2 is a Lorentz scalar; it is evaluated on the partonic centre-of-mass
+             momenta that RAMBO produces (before the boost), where no precision is lost
+             to large rapidities.  Cuts and observables use the lab momenta.
 amp2():      |A|^2 from given momenta, helicity word and colour ordering
 log_weight_int() / log_weight_grad():
              log of the integrand weight without the cut step function and without the
@@ -62,23 +65,29 @@ def amp2(mom, hel, order, ops=NP64):
     return amp2_from_m(ordered_amplitude(k, e), mom.shape[1], ops)
 
 
-def kinematics(cfg: dict, rho, x12, ops=NP64):
-    """RAMBO uniforms [B, n-2, 4] and x12 [B, 2] -> (lab momenta [B, n, 4], s_hat [B])."""
+def _cat(b, p):
+    return np.concatenate([b, p], axis=1) if isinstance(p, np.ndarray) else __import__("torch").cat([b, p], dim=1)
+
+
+def kinematics(cfg: dict, rho, x12, ops=NP64, cm=False):
+    """RAMBO uniforms [B, n-2, 4] and x12 [B, 2] -> (lab momenta [B, n, 4], s_hat [B]);
+    with cm=True also the partonic centre-of-mass momenta [B, n, 4]."""
     if cfg["use_pdf"]:
         x1, x2 = x12[:, 0], x12[:, 1]
         s_hat = x1 * x2 * cfg["sqrt_s"] ** 2
-        p = boost_z(rambo(rho, ops.sqrt(s_hat), ops), x1, x2, ops)
+        pc = rambo(rho, ops.sqrt(s_hat), ops)
+        p = boost_z(pc, x1, x2, ops)
         b = beams(x1, x2, cfg["sqrt_s"], ops)
+        one = 1.0 + 0.0 * x1
+        bc = beams(one, one, ops.sqrt(s_hat), ops)
     else:
         one = 1.0 + 0.0 * rho[:, 0, 0]
         s_hat = one * cfg["sqrt_s"] ** 2
-        p = rambo(rho, ops.sqrt(s_hat), ops)
-        b = beams(one, one, cfg["sqrt_s"], ops)
-    if isinstance(p, np.ndarray):
-        mom = np.concatenate([b, p], axis=1)
-    else:
-        mom = ops.t.cat([b, p], dim=1)
-    return mom, s_hat
+        pc = p = rambo(rho, ops.sqrt(s_hat), ops)
+        bc = b = beams(one, one, cfg["sqrt_s"], ops)
+    if cm:
+        return _cat(b, p), s_hat, _cat(bc, pc)
+    return _cat(b, p), s_hat
 
 
 def generate(cfg: dict, events) -> dict:
@@ -94,11 +103,11 @@ def generate(cfg: dict, events) -> dict:
     else:
         x12 = np.ones((len(events), 2))
         ratio = 1.0
-    mom, s_hat = kinematics(cfg, rho, x12)
+    mom, s_hat, mom_cm = kinematics(cfg, rho, x12, cm=True)
     cut = _cuts.cuts(mom[:, 2:], cfg["pt_min"], cfg["eta_max"], cfg["dr_min"])
-    a2 = amp2(mom, hel, order)
+    a2 = amp2(mom_cm, hel, order)
     w = weight(a2, s_hat, n, cfg["alpha_s"], ratio, cut["pass_"])
-    return dict(x12=x12, rho=rho, hel=hel, order=order, mom=mom, s_hat=s_hat, amp2=a2,
+    return dict(x12=x12, rho=rho, hel=hel, order=order, mom=mom, mom_cm=mom_cm, s_hat=s_hat, amp2=a2,
                 weight=w, pass_=cut["pass_"], ht=cut["ht"], rmin=cut["rmin"],
                 margin=cut["margin"], words=words)
 
@@ -119,8 +128,8 @@ def log_weight_int(cfg: dict, u, x12, hel, order, ops=NP64):
     n = cfg["n"]
     B = u.shape[0]
     rho = u.reshape(B, n - 2, 4)
-    mom, s_hat = kinematics(cfg, rho, x12, ops)
-    k, e = ordered_legs(mom, hel, order, ops)
+    _, s_hat, mom_cm = kinematics(cfg, rho, x12, ops, cm=True)
+    k, e = ordered_legs(mom_cm, hel, order, ops)
     m = ordered_amplitude(k, e)
     la2 = ops.log(amp2_from_m(m, n, ops))
     out = la2 + (n - 5) * ops.log(s_hat) + log_const(n, cfg["alpha_s"])

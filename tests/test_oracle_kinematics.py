@@ -143,3 +143,22 @@ def test_polarisation_properties():
     ep = polarisation(p, np.ones(len(p)))
     em = polarisation(p, -np.ones(len(p)))
     assert np.allclose(mdot(ep, np.conj(em)), 0.0, atol=1e-15)
+
+
+def test_amp2_frame_independence():
+    """|A|^2 is a Lorentz scalar: the generator's centre-of-mass evaluation agrees with the
+    lab-frame one up to the lab frame's own rounding (large rapidities)."""
+    from oracle import event
+    n, N = 7, 300
+    oc = event.config(n=n, use_pdf=1, sqrt_s=14000.0)
+    u = inputs.rambo_uniforms(21, N, n).reshape(N, n - 2, 4)
+    x = inputs.x_fractions(21, N, oc["tau_min"])
+    hel = np.full(N, 0b0100101, dtype=np.uint32)
+    order = inputs.orderings(21, N, n)
+    lab, s_hat, cm = event.kinematics(oc, u, x, cm=True)
+    assert np.allclose(cm.sum(1)[:, 1:], 0.0, atol=1e-9 * np.sqrt(s_hat)[:, None])
+    assert np.allclose(cm[:, :2].sum(1)[:, 0], np.sqrt(s_hat), rtol=1e-14)
+    a_lab = event.amp2(lab, hel, order)
+    a_cm = event.amp2(cm, hel, order)
+    rel = np.abs(a_lab / a_cm - 1)
+    assert np.median(rel) < 1e-12 and np.quantile(rel, 0.9) < 1e-9
