@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the event-generation path on one MI355X.
+
+One step = one bg_generate call over 2^24 gg -> 6g events (n = 8 external gluons):
+Philox draws, x1/x2 from f(x) = x^-1.3 (1-x)^5, RAMBO at sqrt(S) = 14 TeV, the boost, jet
+cuts (pT > 20 GeV, |eta| < 2.5, dR > 0.4) and observables, helicity sources, the
+Berends-Giele recursion in FP32 (kinematics, K^2 and weights in FP64), |A|^2, weights and
+the compensated weight sums.  Inputs are generated on the device from the seed; nothing
+is copied from the host inside the timed region.
+
+Prints one JSON line (see the keys below).  Extra keys report the FP64 run of the same
+workload, the FP32 / FP64 runs of gg -> 10g (n = 12, 2^22 events), the FP32-versus-FP64
+relative error on identical events, and the forward+adjoint rate when available.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12   # MI355X vector FP32 (counts packed FP32; this build emits scalar FP32 only)
+PEAK_FP64 = 78.6e12    # MI355X vector FP64
+PAPER_N8_EVENTS_PER_S = 1.0 / 3.546e-7   # Table 1 of the paper, NVIDIA Tesla, FP32 (context only)
+
+
+def comb(n, k):
+    return math.comb(n, k)
+
+
+def flops_plain(n: int) -> int:
+    """Per-event flops of the recursion in the printed form (3- and 4-gluon brackets summed
+    term by term, complex helicity currents): 146 C(n,3) + 188 C(n,4) + 20 (L(L-1)/2 - 1) + 40 n + 30."""
+    L = n - 1
+    return 146 * comb(n, 3) + 188 * comb(n, 4) + 20 * (L * (L - 1) // 2 - 1) + 40 * n + 30
+
+
+def flops_executed(n: int) -> int:
+    """Per-event floating-point operations the kernel's recursion executes (fma = 2):
+    per span of length l: FP64 span sum 4(l-1); per split: K updates 8 (4 on the first),
+    complex dot 30, two complex-real dots 28, two complex axpys 64 (+2 negations),
+    (K_A - K_B) 4, its axpy 16, S 2; per pair of splits: dot 30 + axpy 32; 2(l-2) S-terms of 34;
+    V = 2X + Y 16; then propagator 16 or closure dot 30."""
+    L = n - 1
+    tot = 0
+    for length in range(2, L + 1):
+        spans = L - length + 1
+        s = length - 1
+        per = 4 * (length - 1) + s * 154 - 4 + 62 * comb(length - 1, 2) + 34 * 2 * (length - 2) + 16
+        per += 16 if length < L else 30
+        tot += spans * per
+    return tot
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1002_3446_amd", "csrc"))):
+        h.update(open(os.path.join(ROOT, "paper_1002_3446_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were taken
+    on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_steps(bg, torch, cfg, N, steps, warmup, outputs):
+    """Returns (wall seconds over the timed steps, list of per-launch device ms, outputs)."""
+    first = cfg.first_event
+    out = bg.generate(cfg, N, outputs=outputs)          # first call allocates the outputs
+    torch.cuda.synchronize()
+    for s in range(warmup):
+        cfg.first_event = first + (s + 1) * N
+        out["acc"].zero_()
+        bg.generate(cfg, N, outputs=outputs, out_tensors=[out])
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        cfg.first_event = first + (warmup + 1 + s) * N
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        bg.generate(cfg, N, outputs=outputs, out_tensors=[out])
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cfg.first_event = first
+    return wall, [a.elapsed_time(b) for a, b in evs], out
+
+
+def live_helicities(hel, n, torch):
+    """Mask of helicity words with at least two of each helicity (non-vanishing amplitudes)."""
+    bits = (hel.unsqueeze(1) >> torch.arange(n, device=hel.device, dtype=hel.dtype)) & 1
+    plus = bits.sum(1)
+    return (plus >= 2) & (plus <= n - 2)
+
+
+def cpu_baseline(seconds: float = 12.0):
+    """The oracle (numpy, one thread) on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import event
+    oc = event.config(n=8, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
+    chunk = 4096
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        event.generate(oc, np.arange(done, done + chunk))
+        done += chunk
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="events/s", cores=1, kind="oracle",
+                sample=f"first {done} events of the n=8 workload (seed 0xB6000001), numpy float64, one thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--events", type=int, default=1 << 24)
+    ap.add_argument("--no-extras", action="store_true", help="main line only (used under profilers)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); events are independent, "
+              "so N GPUs would run disjoint Philox event ranges and add their compensated sums.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1002_3446_amd import bg
+
+    torch.cuda.set_device(0)
+    outputs = ("weight", "amp2", "obs", "pass", "acc")
+    n, N = 8, a.events
+    cfg = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
+    wall, ms, out = run_steps(bg, torch, cfg, N, a.steps, a.warmup, outputs)
+    ms_step = 1e3 * wall / a.steps
+    value = N * a.steps / wall
+    launch_ms = sum(ms) / len(ms)
+    fp = flops_plain(n)
+    fe = flops_executed(n)
+    achieved = fp * N / (launch_ms * 1e-3)
+    line = {
+        "metric": "events/s at gg->6g (n=8) FP32 recursion (FP64 kinematics and weights), full generation path",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 recursion + f64 kinematics/weights",
+        "data": "synthetic: Philox-seeded RAMBO events generated on the device",
+        "config": {"workload": "gg->6g (8 external gluons), 2^24 events per step, sqrt(S)=14 TeV, "
+                               "x ~ x^-1.3 (1-x)^5 on [7.35e-5,1), alpha_s=0.118, random helicity and "
+                               "colour ordering per event, cuts pT>20 GeV |eta|<2.5 dR>0.4",
+                   "n": n, "events_per_step": N, "prec": 32, "parallelism": "one event per lane, 1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": traffic_from_profile("k_generate<8,float>"),
+                     "kernel": "k_generate<8,float>", "launch_ms": launch_ms,
+                     "flops_per_event_plain": fp, "flops_per_event_executed": fe,
+                     "executed_tflops": fe * N / (launch_ms * 1e-3) / 1e12,
+                     "executed_frac": fe * N / (launch_ms * 1e-3) / PEAK_FP32},
+        "paper_context": {"tesla_fp32_n8_events_per_s": PAPER_N8_EVENTS_PER_S,
+                          "note": "paper Table 1, NVIDIA Tesla, real polarisations, LHAPDF; not the same workload"},
+    }
+    acc = out["acc"].cpu().numpy()
+    line["sigma_pb_last_step"] = float((acc[0] + acc[1]) / N)
+
+    if not a.no_extras:
+        extras = {}
+        cfg64 = bg.config(n, prec=64, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
+        w64, ms64, out64 = run_steps(bg, torch, cfg64, N, max(2, a.steps // 3), 1, outputs)
+        extras["n8_fp64_events_per_s"] = N * max(2, a.steps // 3) / w64
+        extras["n8_fp64_launch_ms"] = sum(ms64) / len(ms64)
+        # FP32 versus FP64 on identical events (kinematics are FP64 in both), over helicity
+        # configurations whose amplitude does not vanish identically
+        r32 = bg.generate(cfg, 1 << 20, outputs=("amp2", "hel"))
+        a32, hel = r32["amp2"], r32["hel"]
+        a64 = bg.generate(cfg64, 1 << 20, outputs=("amp2",))["amp2"]
+        rel = ((a32 - a64).abs() / a64.abs())[live_helicities(hel, n, torch)]
+        q = torch.quantile(rel[:1 << 20].float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
+        extras["n8_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
+        n12, N12 = 12, 1 << 22
+        for prec in (32, 64):
+            c12 = bg.config(n12, prec=prec, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000002)
+            st = 3 if prec == 32 else 2
+            w12, ms12, _ = run_steps(bg, torch, c12, N12, st, 1, outputs)
+            extras[f"n12_fp{prec}_events_per_s"] = N12 * st / w12
+            extras[f"n12_fp{prec}_launch_ms"] = sum(ms12) / len(ms12)
+            extras[f"n12_fp{prec}_frac_plain"] = flops_plain(12) * N12 / (sum(ms12) / len(ms12) * 1e-3) / (PEAK_FP32 if prec == 32 else PEAK_FP64)
+        c12a = bg.config(12, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000002)
+        c12b = bg.config(12, prec=64, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000002)
+        r32 = bg.generate(c12a, 1 << 18, outputs=("amp2", "hel"))
+        b64 = bg.generate(c12b, 1 << 18, outputs=("amp2",))["amp2"]
+        rel = ((r32["amp2"] - b64).abs() / b64.abs())[live_helicities(r32["hel"], 12, torch)]
+        q = torch.quantile(rel.float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
+        extras["n12_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
+        line["extras"] = extras
+
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

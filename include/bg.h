@@ -1,0 +1,142 @@
+/* bg.h - C ABI of libbg: leading-colour gg -> (n-2) g tree amplitudes by Berends-Giele
+ * recursion, RAMBO phase space, jet cuts and event weights, one event per GPU lane,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: W. T. Giele, G. C. Stavenga, J. Winter, "Thread-Scalable Evaluation of
+ * Multi-Jet Observables" (FERMILAB-PUB-10-025-T):
+ *   Sec. 3, Eq. 3.1-3.2   the recursion for colour-ordered off-shell currents,
+ *   Sec. 3, Eq. 3.5-3.6   the amputated closure m of the ordered amplitude,
+ *   Sec. 3, Eq. 3.7-3.8   leading colour and the random-ordering cross section,
+ *   Sec. 3 (text)         RAMBO phase space, flag-only jet cuts, observables,
+ *   Sec. 4                jet cuts pT > 20 GeV, |eta| < 2.5, dR > 0.4; compensated sums.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers to per-event arrays are HIP device pointers owned by the caller; every
+ *     array is dense, row-major, with the layout stated at each argument.  The library
+ *     keeps no pointer after the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and the call
+ *     returns without synchronising.  A kernel fault surfaces at the caller's next
+ *     synchronisation of that stream.
+ *   - Host-side argument errors return a negative bg_status before anything is
+ *     enqueued; a failed HIP launch or allocation returns BG_EHIP / BG_ENOMEM.  No C++
+ *     exception crosses this interface.
+ *   - Momenta are (E, px, py, pz) in GeV, metric (+,-,-,-).  Legs 0 and 1 are the
+ *     incoming partons along +z and -z; legs 2..n-1 the outgoing gluons.
+ *   - A helicity word has bit i set when leg i has all-outgoing helicity +.
+ *   - A colour ordering is n bytes: order[0] is the closing leg (always 0 for
+ *     generated events), order[1..n-1] the ordered recursion legs.  Per-event array
+ *     contents (that order is a permutation, that momenta conserve) are not checked.
+ *   - |A|^2 is reported in the Parke-Taylor normalisation (Tr(T^a T^b) = delta^ab):
+ *     the printed brackets of Eq. 3.2 carry coefficient 1, so |m|^2 = 2^(n-2) |A|^2.
+ */
+#ifndef BG_H
+#define BG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BG_OK = 0,
+  BG_EINVAL = -1,   /* NULL required pointer, bad size or inconsistent configuration */
+  BG_ENOTSUP = -2,  /* n outside 4..12, prec not 32 or 64 */
+  BG_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+  BG_ENOMEM = -4    /* device workspace could not be allocated */
+} bg_status;
+
+/* One event class (Sec. 3, Eq. 3.8 with the synthetic density replacing LHAPDF). */
+typedef struct {
+  int32_t n;            /* external gluons, 4..12 */
+  int32_t prec;         /* 32 or 64: precision of helicity vectors, currents and closure;
+                           phase space, cuts, span invariants K^2 and weights are FP64 */
+  double sqrt_s;        /* GeV: collider sqrt(S) when use_pdf = 1, else the fixed sqrt(s_hat) */
+  int32_t use_pdf;      /* 1: x1, x2 drawn from f(x) = x^pdf_a (1-x)^pdf_b on [tau_min, 1) */
+  int32_t pdf_b;        /* integer exponent b, 0..16 */
+  double pdf_a;         /* exponent a; a + k + 1 must not vanish for k = 0..b */
+  double tau_min;       /* lower end of x; <= 0 means ((n-2) pt_min / sqrt_s)^2 */
+  double alpha_s;       /* fixed strong coupling, g^2 = 4 pi alpha_s */
+  double pt_min;        /* GeV; cut pT > pt_min on every outgoing gluon */
+  double eta_max;       /* cut |eta| < eta_max */
+  double dr_min;        /* cut Delta R > dr_min on every outgoing pair */
+  int32_t random_order; /* 1: colour ordering drawn per event (Eq. 3.8); 0: identity */
+  int32_t reserved;     /* must be 0 */
+  uint64_t seed;        /* Philox-4x32-10 key */
+  uint64_t first_event; /* event index of the first event (Philox counter offset) */
+} bg_config;
+
+/* Optional caller-supplied draws for bg_generate; any NULL field is drawn from Philox.
+ * Used to evaluate given phase-space points (tests, the log-weight gradient). */
+typedef struct {
+  const double *uniforms;  /* [N][4(n-2)]: rho1..rho4 of outgoing gluons 2..n-1, in (0,1) */
+  const double *x12;       /* [N][2]: x1, x2 VALUES in [tau_min, 1) (ignored unless use_pdf) */
+  const uint32_t *hel;     /* [N] helicity words */
+  const uint8_t *order;    /* [N][n] colour orderings */
+} bg_inputs;
+
+/* Per-class outputs; every pointer may be NULL (skipped). */
+typedef struct {
+  double *weight;    /* [N] event weight in pb; exactly 0 when the event fails the cuts */
+  double *amp2;      /* [N] |A(sigma; h)|^2, GeV^(2(4-n)), computed for every event */
+  double *obs;       /* [N][2] H_T = sum pT (GeV), R_min = min Delta R */
+  uint8_t *pass;     /* [N] 1 when the event passes all cuts */
+  double *momenta;   /* [N][n][4] lab-frame physical momenta */
+  uint32_t *hel;     /* [N] helicity words used */
+  uint8_t *order;    /* [N][n] colour orderings used */
+  double *x12;       /* [N][2] x1, x2 used (1, 1 when use_pdf = 0) */
+  double *uniforms;  /* [N][4(n-2)] RAMBO uniforms used */
+  double *acc;       /* [4] sum w, its compensation, sum w^2, its compensation; the call's
+                        compensated totals are ADDED (caller zeroes before the first call) */
+} bg_outputs;
+
+/* Generate events of ncfg classes in one launch (Sec. 3; mixed multiplicities when
+ * ncfg > 1).  Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
+ * event i of a class is a pure function of (seed, first_event + i, n) and of
+ * ins[k] when given, so split runs reproduce an unsplit run event by event.
+ * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
+ * counts[k] = 0 is allowed.  Errors: BG_EINVAL (ncfg < 1 or > 16, counts < 0,
+ * bad parameters), BG_ENOTSUP (n or prec). */
+int bg_generate(const bg_config *cfgs, int ncfg, const int64_t *counts,
+                const bg_inputs *ins, const bg_outputs *outs, void *stream);
+
+/* |A(sigma; h)|^2 for given physical momenta (Sec. 3, Eqs. 3.1, 3.2, 3.6).
+ * mom [N][n][4] FP64, hel [N], order [N][n]; amp2_out [N] FP64.  Span invariants K^2
+ * are formed in FP64 for both precisions.  N = 0 is a no-op. */
+int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
+            const uint8_t *order, double *amp2_out, void *stream);
+
+/* Gradient of the log integrand weight (Eq. 3.8 without the cut step function and
+ * without the sampling density),
+ *   log w_int = log f(x1) + log f(x2) - log(2 s_hat) + log V_{n-2}(s_hat)
+ *               + log(colour, helicity and ordering factors) + log |A|^2,
+ * with respect to the RAMBO uniforms and x1, x2, by a hand-written adjoint of
+ * closure, recursion, helicity vectors, boost and RAMBO.  The forward pass is
+ * recomputed inside the kernel.
+ * cfg: host pointer (n, prec, sqrt_s, use_pdf, pdf_a, pdf_b, alpha_s are used);
+ * uniforms [N][4(n-2)], x12 [N][2] (ignored unless use_pdf), hel [N], order [N][n];
+ * gout [N] (dL/dlog w, may be NULL = all ones); grad_u [N][4(n-2)], grad_x [N][2]
+ * (zeros when use_pdf = 0) receive gout * d log w_int; logw [N] optional.
+ * Events with |A|^2 = 0 get log w = -inf and zero gradients. */
+int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const double *x12,
+                 const uint32_t *hel, const uint8_t *order, const double *gout,
+                 double *grad_u, double *grad_x, double *logw, void *stream);
+
+/* Launch shape for one (n, prec) class: threads per workgroup (64, 128 or 256) and
+ * workgroups per compute unit for the persistent multi-class launch (1..8).
+ * The autotuner writes these; 0 restores the built-in default.  Affects speed only:
+ * per-event outputs are identical for every shape.  Errors: BG_ENOTSUP, BG_EINVAL. */
+int bg_set_launch(int n, int prec, int block, int blocks_per_cu);
+int bg_get_launch(int n, int prec, int *block, int *blocks_per_cu);
+
+/* Static message for a status code. */
+const char *bg_strerror(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int bg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BG_H */

@@ -1,0 +1,205 @@
+"""ctypes binding of libbg (include/bg.h): argument marshalling only.
+
+Every step of the event path runs in the HIP kernels of libbg.so; this module only
+checks torch tensors (device, dtype, contiguity, shape), builds the C structs and passes
+torch's current stream.  Importing it fails loudly when libbg.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1002_3446_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+BG_OK, BG_EINVAL, BG_ENOTSUP, BG_EHIP, BG_ENOMEM = 0, -1, -2, -3, -4
+
+
+class BgConfig(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("prec", ctypes.c_int32), ("sqrt_s", ctypes.c_double),
+        ("use_pdf", ctypes.c_int32), ("pdf_b", ctypes.c_int32), ("pdf_a", ctypes.c_double),
+        ("tau_min", ctypes.c_double), ("alpha_s", ctypes.c_double), ("pt_min", ctypes.c_double),
+        ("eta_max", ctypes.c_double), ("dr_min", ctypes.c_double), ("random_order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("first_event", ctypes.c_uint64),
+    ]
+
+
+class BgInputs(ctypes.Structure):
+    _fields_ = [("uniforms", ctypes.c_void_p), ("x12", ctypes.c_void_p), ("hel", ctypes.c_void_p),
+                ("order", ctypes.c_void_p)]
+
+
+OUTPUT_FIELDS = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12", "uniforms", "acc")
+
+
+class BgOutputs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in OUTPUT_FIELDS]
+
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_lib.bg_generate.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int, _i64p, ctypes.POINTER(BgInputs),
+                             ctypes.POINTER(BgOutputs), ctypes.c_void_p]
+_lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 5
+_lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 10
+_lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
+_lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.bg_strerror.restype = ctypes.c_char_p
+_lib.bg_strerror.argtypes = [ctypes.c_int]
+for _f in ("bg_generate", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class BgError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn}: {_lib.bg_strerror(status).decode()} (status {status})")
+        self.status = status
+
+
+def _check(fn: str, status: int):
+    if status != BG_OK:
+        raise BgError(fn, status)
+
+
+def version() -> int:
+    return _lib.bg_version()
+
+
+def strerror(status: int) -> str:
+    return _lib.bg_strerror(status).decode()
+
+
+def config(n: int, prec: int = 32, sqrt_s: float = 14000.0, use_pdf: int = 1, pdf_a: float = -1.3,
+           pdf_b: int = 5, tau_min: float = 0.0, alpha_s: float = 0.118, pt_min: float = 20.0,
+           eta_max: float = 2.5, dr_min: float = 0.4, random_order: int = 1, seed: int = 0,
+           first_event: int = 0) -> BgConfig:
+    return BgConfig(n, prec, sqrt_s, use_pdf, pdf_b, pdf_a, tau_min, alpha_s, pt_min, eta_max, dr_min,
+                    random_order, 0, seed, first_event)
+
+
+def _ptr(t, dtype, shape, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+_OUT_SPEC = {  # name -> (dtype, shape given N and n)
+    "weight": (torch.float64, lambda N, n: (N,)),
+    "amp2": (torch.float64, lambda N, n: (N,)),
+    "obs": (torch.float64, lambda N, n: (N, 2)),
+    "pass": (torch.uint8, lambda N, n: (N,)),
+    "momenta": (torch.float64, lambda N, n: (N, n, 4)),
+    "hel": (torch.int32, lambda N, n: (N,)),
+    "order": (torch.uint8, lambda N, n: (N, n)),
+    "x12": (torch.float64, lambda N, n: (N, 2)),
+    "uniforms": (torch.float64, lambda N, n: (N, 4 * (n - 2))),
+    "acc": (torch.float64, lambda N, n: (4,)),
+}
+
+
+def generate(cfgs, counts, inputs=None, outputs=("weight", "amp2", "obs", "pass", "acc"), device="cuda",
+             out_tensors=None):
+    """Runs bg_generate over one or more classes.
+
+    cfgs: BgConfig or list of them; counts: int or list; inputs: None or (list of) dicts
+    with optional 'uniforms', 'x12', 'hel' (int32 words), 'order' tensors; outputs: names
+    to allocate (helicity words come back as int32 tensors holding the uint32 bits).
+    Returns a list of dicts of tensors (a single dict for a single class)."""
+    single = isinstance(cfgs, BgConfig)
+    cfgs = [cfgs] if single else list(cfgs)
+    counts = [counts] if single else list(counts)
+    if inputs is not None and isinstance(inputs, dict):
+        inputs = [inputs]
+    k = len(cfgs)
+    carr = (BgConfig * k)(*cfgs)
+    narr = (ctypes.c_int64 * k)(*counts)
+    outs = (BgOutputs * k)()
+    ins = (BgInputs * k)() if inputs is not None else None
+    results = []
+    keep = []
+    for j, (c, N) in enumerate(zip(cfgs, counts)):
+        n = c.n
+        res = {}
+        for name in outputs:
+            dt, sh = _OUT_SPEC[name]
+            if out_tensors is not None and name in out_tensors[j]:
+                t = out_tensors[j][name]
+            else:
+                t = torch.zeros(sh(N, n), dtype=dt, device=device)
+            setattr(outs[j], name, _ptr(t, dt, sh(N, n), name))
+            res[name] = t
+        if ins is not None and inputs[j] is not None:
+            d = inputs[j]
+            ins[j].uniforms = _ptr(d.get("uniforms"), torch.float64, (N, 4 * (n - 2)), "uniforms")
+            ins[j].x12 = _ptr(d.get("x12"), torch.float64, (N, 2), "x12")
+            ins[j].hel = _ptr(d.get("hel"), torch.int32, (N,), "hel")
+            ins[j].order = _ptr(d.get("order"), torch.uint8, (N, n), "order")
+            keep.append(d)
+        results.append(res)
+    st = _lib.bg_generate(carr, k, narr, ins, outs, _stream(torch.device(device)))
+    _check("bg_generate", st)
+    return results[0] if single else results
+
+
+def amp2(n: int, prec: int, mom, hel, order, out=None):
+    """|A(sigma;h)|^2 for momenta [N, n, 4] float64, hel [N] int32 words, order [N, n] uint8."""
+    N = mom.shape[0]
+    if out is None:
+        out = torch.empty(N, dtype=torch.float64, device=mom.device)
+    st = _lib.bg_amp2(n, prec, N, _ptr(mom, torch.float64, (N, n, 4), "mom"), _ptr(hel, torch.int32, (N,), "hel"),
+                      _ptr(order, torch.uint8, (N, n), "order"), _ptr(out, torch.float64, (N,), "out"),
+                      _stream(mom.device))
+    _check("bg_amp2", st)
+    return out
+
+
+def amp2_grad(cfg: BgConfig, u, x12, hel, order, gout=None, want_logw=True):
+    """(grad_u [N, 4(n-2)], grad_x [N, 2], log w_int [N]) of the log integrand weight."""
+    N = u.shape[0]
+    n = cfg.n
+    gu = torch.empty((N, 4 * (n - 2)), dtype=torch.float64, device=u.device)
+    gx = torch.empty((N, 2), dtype=torch.float64, device=u.device)
+    lw = torch.empty(N, dtype=torch.float64, device=u.device) if want_logw else None
+    st = _lib.bg_amp2_grad(ctypes.byref(cfg), N, _ptr(u, torch.float64, (N, 4 * (n - 2)), "u"),
+                           _ptr(x12, torch.float64, (N, 2), "x12"), _ptr(hel, torch.int32, (N,), "hel"),
+                           _ptr(order, torch.uint8, (N, n), "order"), _ptr(gout, torch.float64, (N,), "gout"),
+                           _ptr(gu, torch.float64, (N, 4 * (n - 2)), "grad_u"),
+                           _ptr(gx, torch.float64, (N, 2), "grad_x"),
+                           _ptr(lw, torch.float64, (N,), "logw") if lw is not None else None,
+                           _stream(u.device))
+    _check("bg_amp2_grad", st)
+    return gu, gx, lw
+
+
+def set_launch(n: int, prec: int, block: int, blocks_per_cu: int):
+    _check("bg_set_launch", _lib.bg_set_launch(n, prec, block, blocks_per_cu))
+
+
+def get_launch(n: int, prec: int):
+    b, c = ctypes.c_int(), ctypes.c_int()
+    _check("bg_get_launch", _lib.bg_get_launch(n, prec, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value
+
+
+def raw():
+    """The loaded ctypes library (for ABI tests)."""
+    return _lib

@@ -1,0 +1,78 @@
+"""Builds libbg.so for gfx950 in-tree: one object per multiplicity (kernels fully unrolled
+per n) plus the C-ABI layer, compiled in parallel with hipcc, then linked shared.
+
+Usage: python -m paper_1002_3446_amd.build [--jobs J]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+OUT_DIR = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libbg.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
+    # packed FP32 instructions stay disabled (only scalar FP32 VALU forms are emitted)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the recursion is unrolled completely per multiplicity so currents stay in registers
+    "-mllvm", "-pragma-unroll-threshold=100000000",
+]
+
+
+def _compile(src: str, obj: str, defines: list[str]) -> str:
+    cmd = [HIPCC, *FLAGS, *defines, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {obj}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+KINDS = (0, 1)  # 0 generate, 1 amp2
+
+
+def units_for(ns, precs=(32, 64), kinds=KINDS):
+    units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"), [], 0),
+             (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0)]
+    for n in ns:
+        for p in precs:
+            for k in kinds:
+                obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}.o")
+                units.append((os.path.join(CSRC, "bg_inst.hip"), obj,
+                              [f"-DBG_N={n}", f"-DBG_PREC={p}", f"-DBG_KIND={k}"], n * (2 if p == 64 else 1)))
+    # the largest multiplicities take longest to compile: start them first
+    units.sort(key=lambda u: -u[3])
+    return units
+
+
+def build(jobs: int | None = None, verbose: bool = True, ns=range(4, 13)) -> str:
+    """Compiles every unit for the multiplicities ns and links libbg.so."""
+    os.makedirs(OUT_DIR, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    units = units_for(list(ns))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units))
+    tmp = LIB + ".tmp"
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}", file=sys.stderr)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--ns", type=str, default="4,5,6,7,8,9,10,11,12",
+                    help="comma-separated multiplicities to build (others report BG_ENOTSUP)")
+    a = ap.parse_args()
+    build(a.jobs, ns=[int(x) for x in a.ns.split(",")])

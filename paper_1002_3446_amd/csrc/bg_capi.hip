@@ -1,0 +1,263 @@
+// C-ABI of libbg (include/bg.h): argument checking, per-class constants, launch shapes,
+// stream-ordered workspace for the compensated reduction, and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/bg.h"
+#include "bg_launch.hpp"
+
+// Launchers of every (kind, n, prec) translation unit; weak, so a library built for a
+// subset of multiplicities reports BG_ENOTSUP for the others.
+#define BG_DECL_ONE(N, P)                                                                                  \
+  __attribute__((weak)) hipError_t launch_generate_n##N##_p##P##_k0(const GenClass&, double*, int,        \
+                                                                    hipStream_t);                         \
+  __attribute__((weak)) hipError_t launch_amp2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*,  \
+                                                                const uint8_t*, double*, int, hipStream_t); \
+  __attribute__((weak)) hipError_t launch_grad_n##N##_p##P##_k2(const GradArgs&, int, hipStream_t);
+#define BG_DECL(N) BG_DECL_ONE(N, 32) BG_DECL_ONE(N, 64)
+namespace bgk {
+BG_DECL(4) BG_DECL(5) BG_DECL(6) BG_DECL(7) BG_DECL(8) BG_DECL(9) BG_DECL(10) BG_DECL(11) BG_DECL(12)
+}
+
+namespace {
+
+using namespace bgk;
+
+#define BG_ROW(N)                                                                                       \
+  {{launch_generate_n##N##_p32_k0, launch_amp2_n##N##_p32_k1, launch_grad_n##N##_p32_k2},               \
+   {launch_generate_n##N##_p64_k0, launch_amp2_n##N##_p64_k1, launch_grad_n##N##_p64_k2}}
+
+const Launchers* table(int n, int prec) {
+  static const Launchers t[9][2] = {BG_ROW(4),  BG_ROW(5),  BG_ROW(6), BG_ROW(7), BG_ROW(8),
+                                    BG_ROW(9), BG_ROW(10), BG_ROW(11), BG_ROW(12)};
+  if (n < 4 || n > 12) return nullptr;
+  if (prec != 32 && prec != 64) return nullptr;
+  return &t[n - 4][prec == 32 ? 0 : 1];
+}
+
+// launch shapes per (n, prec): threads per workgroup and workgroups per CU
+struct Shape {
+  int block, per_cu;
+};
+std::mutex g_shape_mu;
+Shape g_shape[13][2];
+const Shape kDefaultShape{256, 1};
+
+Shape shape_of(int n, int prec) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  Shape s = g_shape[n][prec == 32 ? 0 : 1];
+  if (s.block == 0) s = kDefaultShape;
+  return s;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHbarc2Pb = 0.3893793721e9;  // (hbar c)^2 in pb GeV^2
+constexpr double kNc = 3.0;
+
+double lfact(int k) { return std::lgamma((double)k + 1.0); }
+
+// log of the event-independent factors of the integrand weight (Eq. 3.8 with Eq. 3.7):
+// flux 1/2, massless (n-2)-body volume constant, 1/(n-2)!, 2^n (n-1)! helicity and ordering
+// factors, g^(2(n-2)) N^(n-2) / (4 (N^2-1)) colour factor, (hbar c)^2.
+double log_weight_const(int n, double alpha_s) {
+  const int nf = n - 2;
+  const double lv = (4 - 3 * nf) * std::log(2 * kPi) + (nf - 1) * std::log(kPi / 2) - lfact(nf - 1) - lfact(nf - 2);
+  const double g2 = 4 * kPi * alpha_s;
+  const double lme = n * std::log(2.0) + lfact(n - 1) + (n - 2) * std::log(g2) + (n - 2) * std::log(kNc) -
+                     std::log(4.0 * (kNc * kNc - 1.0));
+  return lv - lfact(n - 2) + lme + std::log(kHbarc2Pb) - std::log(2.0);
+}
+
+// binomial(b, k)
+double binom(int b, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (b - k + i) / i;
+  return r;
+}
+
+int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_outputs* out, GenClass& G) {
+  if (c.n < 4 || c.n > 12 || (c.prec != 32 && c.prec != 64)) return BG_ENOTSUP;
+  if (count < 0 || c.reserved != 0 || !(c.sqrt_s > 0) || (c.use_pdf != 0 && c.use_pdf != 1) ||
+      (c.random_order != 0 && c.random_order != 1) || !(c.alpha_s > 0) || !(c.pt_min >= 0) ||
+      !(c.eta_max > 0) || !(c.dr_min >= 0))
+    return BG_EINVAL;
+  std::memset(&G, 0, sizeof(G));
+  G.count = count;
+  G.first_event = c.first_event;
+  G.key0 = (uint32_t)c.seed;
+  G.key1 = (uint32_t)(c.seed >> 32);
+  G.use_pdf = c.use_pdf;
+  G.random_order = c.random_order;
+  G.sqrt_s = c.sqrt_s;
+  G.pt_min = c.pt_min;
+  G.eta_max = c.eta_max;
+  G.dr_min = c.dr_min;
+  double ratio = 1.0;
+  if (c.use_pdf) {
+    if (c.pdf_b < 0 || c.pdf_b > 16) return BG_EINVAL;
+    double tau = c.tau_min;
+    if (!(tau > 0)) tau = std::pow((c.n - 2) * c.pt_min / c.sqrt_s, 2);
+    if (!(tau > 0 && tau < 1)) return BG_EINVAL;
+    PdfParams& P = G.pdf;
+    P.a = c.pdf_a;
+    P.b = c.pdf_b;
+    P.tau = tau;
+    double ptau = 0.0, p1 = 0.0;
+    for (int k = 0; k <= c.pdf_b; ++k) {
+      const double e = c.pdf_a + k + 1.0;
+      if (e == 0.0) return BG_EINVAL;
+      P.coef[k] = binom(c.pdf_b, k) * ((k & 1) ? -1.0 : 1.0) / e;
+    }
+    for (int k = c.pdf_b; k >= 0; --k) {
+      ptau = ptau * tau + P.coef[k];
+      p1 += P.coef[k];
+    }
+    P.x0base = std::pow(tau, c.pdf_a + 1.0);
+    P.Ftau = P.x0base * ptau;
+    P.F1 = p1;
+    P.Z = p1 - P.Ftau;
+    if (!(P.Z > 0)) return BG_EINVAL;
+    // branch point of the sampler: x_split = 0.2 (or the midpoint of [tau, 1) if tau >= 0.2)
+    P.xsplit = tau < 0.2 ? 0.2 : 0.5 * (tau + 1.0);
+    double psplit = 0.0;
+    for (int k = c.pdf_b; k >= 0; --k) psplit = psplit * P.xsplit + P.coef[k];
+    P.usplit = (std::pow(P.xsplit, c.pdf_a + 1.0) * psplit - P.Ftau) / P.Z;
+    ratio = P.Z * P.Z;
+  }
+  G.wconst = ratio * std::exp(log_weight_const(c.n, c.alpha_s));
+  if (in) {
+    G.in_u = in->uniforms;
+    G.in_x = in->x12;
+    G.in_hel = in->hel;
+    G.in_order = in->order;
+  }
+  if (out) {
+    G.out.weight = out->weight;
+    G.out.amp2 = out->amp2;
+    G.out.obs = out->obs;
+    G.out.pass = out->pass;
+    G.out.momenta = out->momenta;
+    G.out.hel = out->hel;
+    G.out.order = out->order;
+    G.out.x12 = out->x12;
+    G.out.uniforms = out->uniforms;
+  }
+  return BG_OK;
+}
+
+int from_hip(hipError_t e) { return e == hipSuccess ? BG_OK : BG_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+int bg_version(void) { return 10000; }
+
+const char* bg_strerror(int status) {
+  switch (status) {
+    case BG_OK: return "ok";
+    case BG_EINVAL: return "invalid argument";
+    case BG_ENOTSUP: return "unsupported multiplicity or precision";
+    case BG_EHIP: return "HIP runtime error";
+    case BG_ENOMEM: return "device workspace allocation failed";
+    default: return "unknown status";
+  }
+}
+
+int bg_set_launch(int n, int prec, int block, int blocks_per_cu) {
+  if (!table(n, prec)) return BG_ENOTSUP;
+  if (block == 0 && blocks_per_cu == 0) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape[n][prec == 32 ? 0 : 1] = Shape{0, 0};
+    return BG_OK;
+  }
+  if (block < 64 || block > 256 || block % 64 != 0 || blocks_per_cu < 1 || blocks_per_cu > 8) return BG_EINVAL;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_shape[n][prec == 32 ? 0 : 1] = Shape{block, blocks_per_cu};
+  return BG_OK;
+}
+
+int bg_get_launch(int n, int prec, int* block, int* blocks_per_cu) {
+  if (!table(n, prec)) return BG_ENOTSUP;
+  if (!block || !blocks_per_cu) return BG_EINVAL;
+  const Shape s = shape_of(n, prec);
+  *block = s.block;
+  *blocks_per_cu = s.per_cu;
+  return BG_OK;
+}
+
+int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg_inputs* ins,
+                const bg_outputs* outs, void* stream) {
+  if (!cfgs || !counts || !outs || ncfg < 1 || ncfg > 16) return BG_EINVAL;
+  GenClass G[16];
+  for (int k = 0; k < ncfg; ++k) {
+    const int st = fill_class(cfgs[k], counts[k], ins ? &ins[k] : nullptr, &outs[k], G[k]);
+    if (st != BG_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < ncfg; ++k) {
+    if (G[k].count == 0) continue;
+    const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
+    if (!L->generate) return BG_ENOTSUP;
+    const Shape sh = shape_of(cfgs[k].n, cfgs[k].prec);
+    const int64_t nblocks = (G[k].count + sh.block - 1) / sh.block;
+    double* partials = nullptr;
+    if (outs[k].acc) {
+      if (hipMallocAsync((void**)&partials, (size_t)nblocks * 4 * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return BG_ENOMEM;
+      }
+    }
+    int st = from_hip(L->generate(G[k], partials, sh.block, s));
+    if (st == BG_OK && partials) st = from_hip(launch_finalize(partials, nblocks, outs[k].acc, s));
+    if (partials) (void)hipFreeAsync(partials, s);
+    if (st != BG_OK) return st;
+  }
+  return BG_OK;
+}
+
+int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, const uint8_t* order,
+            double* amp2_out, void* stream) {
+  const Launchers* L = table(n, prec);
+  if (!L || !L->amp2) return BG_ENOTSUP;
+  if (N < 0) return BG_EINVAL;
+  if (N == 0) return BG_OK;
+  if (!mom || !hel || !order || !amp2_out) return BG_EINVAL;
+  const Shape sh = shape_of(n, prec);
+  return from_hip(L->amp2(N, mom, hel, order, amp2_out, sh.block, (hipStream_t)stream));
+}
+
+int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const double* x12, const uint32_t* hel,
+                 const uint8_t* order, const double* gout, double* grad_u, double* grad_x, double* logw,
+                 void* stream) {
+  if (!cfg) return BG_EINVAL;
+  const Launchers* L = table(cfg->n, cfg->prec);
+  if (!L) return BG_ENOTSUP;
+  if (N < 0) return BG_EINVAL;
+  if (N == 0) return BG_OK;
+  if (!uniforms || !hel || !order || !grad_u || !grad_x || (cfg->use_pdf && !x12)) return BG_EINVAL;
+  if (!(cfg->sqrt_s > 0) || !(cfg->alpha_s > 0) || (cfg->use_pdf != 0 && cfg->use_pdf != 1)) return BG_EINVAL;
+  if (!L->grad) return BG_ENOTSUP;
+  GradArgs G{};
+  G.count = N;
+  G.sqrt_s = cfg->sqrt_s;
+  G.use_pdf = cfg->use_pdf;
+  G.pdf_a = cfg->pdf_a;
+  G.pdf_b = cfg->pdf_b;
+  G.u = uniforms;
+  G.x12 = x12;
+  G.hel = hel;
+  G.order = order;
+  G.gout = gout;
+  G.grad_u = grad_u;
+  G.grad_x = grad_x;
+  G.logw = logw;
+  G.log_const = log_weight_const(cfg->n, cfg->alpha_s);
+  const Shape sh = shape_of(cfg->n, cfg->prec);
+  return from_hip(L->grad(G, sh.block, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,437 @@
+// Device building blocks of the event path, one event per lane (gfx950).
+//
+// Paper: Giele, Stavenga, Winter, "Thread-Scalable Evaluation of Multi-Jet Observables".
+//   philox4x32        counter-based draws (generator unnamed in the paper, Sec. 4)
+//   pdf_sample        synthetic gluon density x^a (1-x)^b by inverse CDF (stands in for
+//                     the LHAPDF grids of Sec. 3)
+//   rambo_q/rambo_map RAMBO massless phase space (Sec. 3)
+//   polarisation      helicity sources J[i] orthogonal to k_i (Sec. 3)
+//   bg_amplitude      Berends-Giele recursion (Eqs. 3.1, 3.2) and amputated closure (Eq. 3.6)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace bgk {
+
+// Compile-time loop: f(integral_constant<int, I>) for I = B .. E-1.  Every index of the
+// recursion is a constant after instantiation, so the per-lane arrays are scalarised into
+// registers independently of the compiler's unrolling heuristics.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies, key
+// advanced by the Weyl constants between rounds.
+// ----------------------------------------------------------------------------------------
+struct u32x4 {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ u32x4 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return u32x4{{c0, c1, c2, c3}};
+}
+
+// word -> (r + 1/2) 2^-32, exact in double and strictly inside (0, 1)
+__device__ __forceinline__ double u01(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+
+// Draw layout of one event: counter (block, event lo, event hi, n), key (seed lo, seed hi).
+//   block 0: x1 uniform, x2 uniform, helicity word, unused
+//   block 1 + p: rho1..rho4 of outgoing gluon p (leg p + 2)
+//   block n - 1 + k/4, word k%4: shuffle word consumed at Fisher-Yates step t = n-2-k
+struct EventRng {
+  uint32_t e0, e1, n, k0, k1;
+  __device__ __forceinline__ u32x4 block(uint32_t b) const { return philox4x32(b, e0, e1, n, k0, k1); }
+};
+
+// ----------------------------------------------------------------------------------------
+// Colour ordering as nibbles: nibble i holds the leg at recursion position i+1 (legs 1..n-1).
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t nib(uint64_t A, int i) { return (uint32_t)(A >> (4 * i)) & 15u; }
+__device__ __forceinline__ uint64_t set_nib(uint64_t A, int i, uint32_t v) {
+  const uint64_t m = 15ull << (4 * i);
+  return (A & ~m) | ((uint64_t)v << (4 * i));
+}
+
+template <int N>
+__device__ __forceinline__ uint64_t identity_order() {
+  uint64_t A = 0;
+#pragma unroll
+  for (int i = 0; i < N - 1; ++i) A |= (uint64_t)(i + 1) << (4 * i);
+  return A;
+}
+
+// Fisher-Yates over positions 0..N-2 of the nibble list: for t = N-2 .. 1,
+// j = (r_t (t+1)) >> 32, swap entries t and j (Sec. 3: random permutation of legs 2..n).
+template <int N>
+__device__ __forceinline__ uint64_t shuffle_order(const EventRng& rng) {
+  uint64_t A = identity_order<N>();
+  constexpr int NF = N - 2;
+  u32x4 w{};
+#pragma unroll
+  for (int k = 0; k < N - 2; ++k) {
+    if ((k & 3) == 0) w = rng.block(1 + NF + k / 4);
+    const int t = N - 2 - k;
+    const uint32_t r = w.v[k & 3];
+    const uint32_t j = (uint32_t)(((uint64_t)r * (uint64_t)(t + 1)) >> 32);
+    const uint32_t vt = nib(A, t), vj = nib(A, (int)j);
+    A = set_nib(A, t, vj);
+    A = set_nib(A, (int)j, vt);
+  }
+  return A;
+}
+
+// ----------------------------------------------------------------------------------------
+// Synthetic density f(x) = x^a (1-x)^b, b integer, with primitive F(x) = x^(a+1) P(x),
+// P(x) = sum_k C(b,k) (-1)^k x^k / (a+k+1), on [tau, 1); Z = F(1) - F(tau).
+// Inverse CDF by Newton's method in variables where the equation is nearly linear:
+//   x < x_split (u < u_split):  log(F(x) - F(tau)) = log(u Z)        in y = log x,
+//                               then one plain Newton step in x (tiny u: x close to tau);
+//   x >= x_split:               log(F(1) - F(x))   = log((1 - u) Z)  in z = log(1 - x),
+// where 1 - u is exact for u = (r + 1/2) 2^-32.  Converges in 3..7 steps.
+// ----------------------------------------------------------------------------------------
+struct PdfParams {
+  double a, tau, Ftau, F1, Z, x0base;  // x0base = tau^(a+1)
+  double usplit, xsplit;
+  double coef[17];
+  int b;
+};
+
+__device__ __forceinline__ double ipow(double x, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= x;
+  return r;
+}
+
+// F(x) and f(x) with one log and one exp
+__device__ __forceinline__ void pdf_eval(double x, const PdfParams& P, double& F, double& f) {
+  const double xa1 = exp((P.a + 1.0) * log(x));
+  double poly = P.coef[P.b];
+  for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, x, P.coef[k]);
+  F = xa1 * poly;
+  f = xa1 / x * ipow(1.0 - x, P.b);
+}
+
+__device__ inline double pdf_sample(double u, const PdfParams& P) {
+  double x, F, f;
+  if (u < P.usplit) {
+    const double T = u * P.Z;
+    const double target = log(T);
+    const double ap1 = P.a + 1.0;
+    const double base = P.x0base + ap1 * T;  // leading power only
+    x = base > 0.0 ? exp(log(base) / ap1) : P.xsplit;
+    x = fmin(fmax(x, P.tau * (1.0 + 1e-12)), P.xsplit);
+    for (int it = 0; it < 16; ++it) {
+      pdf_eval(x, P, F, f);
+      const double G = F - P.Ftau;
+      if (!(G > 0.0)) {  // stepped below tau: restart just above it
+        x = P.tau * (1.0 + 1e-9);
+        continue;
+      }
+      const double step = (log(G) - target) * G / (x * f);
+      x = x * exp(-step);
+      if (fabs(step) <= 1e-9) break;
+    }
+    pdf_eval(x, P, F, f);
+    x -= (F - P.Ftau - T) / f;
+  } else {
+    const double target = log((1.0 - u) * P.Z);
+    x = 0.5;
+    for (int it = 0; it < 16; ++it) {
+      pdf_eval(x, P, F, f);
+      const double G = P.F1 - F;
+      if (!(G > 0.0)) {
+        x = 0.5 * (x + P.xsplit);
+        continue;
+      }
+      const double step = (log(G) - target) * G / ((1.0 - x) * f);
+      x = -expm1(log1p(-x) - step);
+      if (fabs(step) <= 1e-9) break;
+    }
+  }
+  return x;
+}
+
+// ----------------------------------------------------------------------------------------
+// RAMBO (Sec. 3).  From (rho1..rho4): c = 2 rho1 - 1, phi = 2 pi rho2, q0 = -ln(rho3 rho4),
+// q = q0 (sin cos phi, sin sin phi, c).  Then the conformal map with Q = sum q.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ void rambo_q(double r1, double r2, double r3, double r4, double q[4]) {
+  const double c = 2.0 * r1 - 1.0;
+  const double st = sqrt(1.0 - c * c);
+  double sp, cp;
+  sincospi(2.0 * r2, &sp, &cp);
+  const double q0 = -log(r3 * r4);
+  q[0] = q0;
+  q[1] = q0 * st * cp;
+  q[2] = q0 * st * sp;
+  q[3] = q0 * c;
+}
+
+struct RamboMap {
+  double bx, by, bz, gamma, a, X;
+  __device__ __forceinline__ void init(const double Q[4], double sqrt_shat) {
+    const double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+    bx = -Q[1] / M;
+    by = -Q[2] / M;
+    bz = -Q[3] / M;
+    gamma = Q[0] / M;
+    a = 1.0 / (1.0 + gamma);
+    X = sqrt_shat / M;
+  }
+  __device__ __forceinline__ void apply(const double q[4], double p[4]) const {
+    const double bq = bx * q[1] + by * q[2] + bz * q[3];
+    p[0] = X * (gamma * q[0] + bq);
+    p[1] = X * (q[1] + bx * q[0] + a * bq * bx);
+    p[2] = X * (q[2] + by * q[0] + a * bq * by);
+    p[3] = X * (q[3] + bz * q[0] + a * bq * bz);
+  }
+};
+
+// ----------------------------------------------------------------------------------------
+// Complex four-vectors and the helicity sources.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+struct cv4 {
+  T re[4], im[4];
+};
+
+// eps_h(p) = (0, -h ct cf + i sf, -h ct sf - i cf, h st) / sqrt(2) from the physical momentum
+template <typename T>
+__device__ __forceinline__ cv4<T> polarisation(const double p[4], bool plus) {
+  const double pt2 = p[1] * p[1] + p[2] * p[2];
+  const double pa = sqrt(pt2 + p[3] * p[3]);
+  const double pt = sqrt(pt2);
+  const double ct = p[3] / pa, st = pt / pa;
+  double cf = 1.0, sf = 0.0;
+  if (pt2 > 0.0) {
+    cf = p[1] / pt;
+    sf = p[2] / pt;
+  }
+  const double r = 0.70710678118654752440;
+  const double h = plus ? r : -r;
+  cv4<T> e;
+  e.re[0] = T(0);
+  e.im[0] = T(0);
+  e.re[1] = T(-h * ct * cf);
+  e.im[1] = T(sf * r);
+  e.re[2] = T(-h * ct * sf);
+  e.im[2] = T(-cf * r);
+  e.re[3] = T(h * st);
+  e.im[3] = T(0);
+  return e;
+}
+
+// ----------------------------------------------------------------------------------------
+// Berends-Giele recursion, Eqs. 3.1-3.2, over L ordered legs, followed by the closure of
+// Eq. 3.6.  Spans [a..b] are stored by length, then start.  The four-gluon sum is
+// regrouped exactly: with S[x..y] = sum_k J[x..k].J[k+1..y] (the scalars the three-gluon
+// sum already forms),
+//   sum_{i<j} (JA.JB) JC = sum_j S[a..j] J[j+1..b],   sum_{i<j} (JC.JB) JA = sum_i S[i+1..b] J[a..i],
+// so only 2 (JA.JC) JB is summed over pairs of splits.  Span momenta are never stored:
+// every K[x..y] a bracket needs is summed left to right over its own legs in FP64 and only
+// then cast to T (a difference of longer sums would lose relative precision on soft spans).
+// K^2 and 1/K^2 are FP64, formed without fused multiply-adds, before the cast.
+// ----------------------------------------------------------------------------------------
+// K^2 of an FP64 four-vector, E^2 - px^2 - py^2 - pz^2 in that order, without contraction
+__device__ __forceinline__ double minkowski_sq(const double K[4]) {
+#pragma clang fp contract(off)
+  const double e = K[0] * K[0];
+  const double x = K[1] * K[1];
+  const double y = K[2] * K[2];
+  const double z = K[3] * K[3];
+  return ((e - x) - y) - z;
+}
+
+// left-to-right FP64 sum of the legs A..B
+template <int A, int B, int L>
+__device__ __forceinline__ void span_sum(const double (&k)[L][4], double K[4]) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) K[mu] = k[A][mu];
+  static_for<A + 1, B + 1>([&](auto i) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) K[mu] += k[decltype(i)::value][mu];
+  });
+}
+
+template <int L>
+struct Spans {
+  static constexpr int count = L * (L + 1) / 2;
+  __host__ __device__ static constexpr int at(int a, int b) {
+    return (b - a) * (L + 1) - (b - a) * (b - a + 1) / 2 + a;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void cdot(const cv4<T>& x, const cv4<T>& y, T& r, T& i) {
+  r = x.re[0] * y.re[0] - x.im[0] * y.im[0];
+  i = x.re[0] * y.im[0] + x.im[0] * y.re[0];
+#pragma unroll
+  for (int mu = 1; mu < 4; ++mu) {
+    r -= x.re[mu] * y.re[mu] - x.im[mu] * y.im[mu];
+    i -= x.re[mu] * y.im[mu] + x.im[mu] * y.re[mu];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void rdot(const cv4<T>& x, const T k[4], T& r, T& i) {
+  r = x.re[0] * k[0];
+  i = x.im[0] * k[0];
+#pragma unroll
+  for (int mu = 1; mu < 4; ++mu) {
+    r -= x.re[mu] * k[mu];
+    i -= x.im[mu] * k[mu];
+  }
+}
+
+// acc += (cr + i ci) * y
+template <typename T>
+__device__ __forceinline__ void caxpy(T cr, T ci, const cv4<T>& y, cv4<T>& acc) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    acc.re[mu] += cr * y.re[mu] - ci * y.im[mu];
+    acc.im[mu] += cr * y.im[mu] + ci * y.re[mu];
+  }
+}
+
+// One span [A..B] of the recursion: its bracket sum V (Eqs. 3.1-3.2, regrouped as above).
+template <int L, int A, int B, typename T>
+__device__ __forceinline__ void span_vertex(const double (&k)[L][4], const cv4<T> (&J)[Spans<L>::count],
+                                            const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
+                                            cv4<T>& V, T& sr, T& si, double (&Kd)[4]) {
+  using SP = Spans<L>;
+  span_sum<A, B, L>(k, Kd);
+  cv4<T> X, Y;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) X.re[mu] = X.im[mu] = Y.re[mu] = Y.im[mu] = T(0);
+  sr = T(0);
+  si = T(0);
+  // three-gluon brackets [J[A..i], J[i+1..B]]
+  static_for<A, B>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int PA = SP::at(A, i), PB = SP::at(i + 1, B);
+    double KA[4], KB[4];
+    span_sum<A, i, L>(k, KA);
+    span_sum<i + 1, B, L>(k, KB);
+    T ka[4], kb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      ka[mu] = T(KA[mu]);
+      kb[mu] = T(KB[mu]);
+    }
+    T dr, di, ar, ai, br, bi;
+    cdot(J[PA], J[PB], dr, di);
+    rdot(J[PA], kb, ar, ai);
+    rdot(J[PB], ka, br, bi);
+    caxpy(ar, ai, J[PB], X);
+    caxpy(-br, -bi, J[PA], X);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const T dk = ka[mu] - kb[mu];
+      Y.re[mu] += dr * dk;
+      Y.im[mu] += di * dk;
+    }
+    sr += dr;
+    si += di;
+  });
+  // four-gluon brackets: 2 (JA.JC) JB over pairs of splits
+  static_for<A, B - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    static_for<i + 1, B>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      T dr, di;
+      cdot(J[SP::at(A, i)], J[SP::at(j + 1, B)], dr, di);
+      caxpy(dr, di, J[SP::at(i + 1, j)], X);
+    });
+  });
+  // -(JA.JB) JC and -(JC.JB) JA through the span scalars S
+  static_for<A + 1, B>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    constexpr int Sx = SP::at(A, j);
+    caxpy(-Sr[Sx], -Si[Sx], J[SP::at(j + 1, B)], Y);
+  });
+  static_for<A, B - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int Sx = SP::at(i + 1, B);
+    caxpy(-Sr[Sx], -Si[Sx], J[SP::at(A, i)], Y);
+  });
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    V.re[mu] = T(2) * X.re[mu] + Y.re[mu];
+    V.im[mu] = T(2) * X.im[mu] + Y.im[mu];
+  }
+}
+
+// k: FP64 all-outgoing momenta of the L recursion legs (any common power-of-two scale);
+// src: their sources; eps0: the closing leg's polarisation.  Returns m = eps0 . V.
+template <int L, typename T>
+__device__ __forceinline__ void bg_amplitude(const double (&k)[L][4], const cv4<T> (&src)[L],
+                                             const cv4<T>& eps0, double& m_re, double& m_im) {
+  using SP = Spans<L>;
+  cv4<T> J[SP::count];
+  T Sr[SP::count], Si[SP::count];
+  static_for<0, L>([&](auto ac) { J[decltype(ac)::value] = src[decltype(ac)::value]; });
+  static_for<2, L>([&](auto lc) {
+    constexpr int len = decltype(lc)::value;
+    static_for<0, L - len + 1>([&](auto ac) {
+      constexpr int a = decltype(ac)::value, b = a + len - 1, s = SP::at(a, b);
+      cv4<T> V;
+      T sr, si;
+      double Kd[4];
+      span_vertex<L, a, b, T>(k, J, Sr, Si, V, sr, si, Kd);
+      const T prop = T(1.0 / minkowski_sq(Kd));
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        J[s].re[mu] = V.re[mu] * prop;
+        J[s].im[mu] = V.im[mu] * prop;
+      }
+      Sr[s] = sr;
+      Si[s] = si;
+    });
+  });
+  // the full span: amputated, contracted with the closing polarisation (Eq. 3.6)
+  cv4<T> V;
+  T sr, si;
+  double Kd[4];
+  span_vertex<L, 0, L - 1, T>(k, J, Sr, Si, V, sr, si, Kd);
+  T mr, mi;
+  cdot(eps0, V, mr, mi);
+  m_re = double(mr);
+  m_im = double(mi);
+}
+
+// ----------------------------------------------------------------------------------------
+// Compensated sums: TwoSum (Knuth) pairs (s, c).
+// ----------------------------------------------------------------------------------------
+struct CSum {
+  double s, c;
+};
+
+__device__ __forceinline__ CSum cs_add(CSum x, CSum y) {
+  const double s = x.s + y.s;
+  const double bb = s - x.s;
+  const double e = (x.s - (s - bb)) + (y.s - bb);
+  return CSum{s, x.c + y.c + e};
+}
+
+}  // namespace bgk

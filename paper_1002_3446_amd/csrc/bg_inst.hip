@@ -1,0 +1,39 @@
+// Instantiates one kernel kind (BG_KIND: 0 generate, 1 amp2, 2 gradient) of one
+// multiplicity (BG_N, 4..12) and recursion precision (BG_PREC, 32 or 64), and exports its
+// launcher through a host function resolved by the C-ABI layer.
+#include "bg_kernels.hpp"
+#include "bg_launch.hpp"
+
+#if !defined(BG_N) || !defined(BG_PREC) || !defined(BG_KIND)
+#error "BG_N, BG_PREC and BG_KIND must be defined"
+#endif
+
+#define BG_CAT4(a, b, c, d) a##b##_p##c##_k##d
+#define BG_NAME(a, b, c, d) BG_CAT4(a, b, c, d)
+
+namespace bgk {
+
+#if BG_PREC == 32
+using Real = float;
+#else
+using Real = double;
+#endif
+
+#if BG_KIND == 0
+hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
+                                                              hipStream_t s) {
+  const int64_t nb = (C.count + block - 1) / block;
+  hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, C, partials);
+  return hipGetLastError();
+}
+#elif BG_KIND == 1
+hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
+                                                          const uint8_t* order, double* out, int block,
+                                                          hipStream_t s) {
+  const int64_t nb = (count + block - 1) / block;
+  hipLaunchKernelGGL((k_amp2<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
+  return hipGetLastError();
+}
+#endif
+
+}  // namespace bgk

@@ -1,0 +1,280 @@
+// Kernels of the event path: one event per lane, everything for that event kept in the
+// lane's registers.  Instantiated per multiplicity N (4..12) and recursion precision T.
+#pragma once
+
+#include "bg_device.hpp"
+#include "bg_params.hpp"
+
+namespace bgk {
+
+// Lab-frame physical momenta of all N legs in recursion-position order (position 0 is
+// leg 0, position t >= 1 is leg nib(A, t-1)), with the per-event draws and kinematics.
+template <int N>
+struct EventKin {
+  double p[N][4];   // physical lab momenta, position order
+  double pc[N][4];  // partonic centre-of-mass momenta (RAMBO frame), position order
+  uint32_t leg[N];  // leg at each position
+  uint32_t hel;
+  double x1, x2, shat;
+};
+
+// Builds an event's phase-space point (Sec. 3: RAMBO then the longitudinal boost) from
+// Philox draws or from caller inputs; writes the optional draw outputs.
+template <int N>
+__device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventKin<N>& ev) {
+  constexpr int NF = N - 2;
+  const uint64_t e = C.first_event + (uint64_t)i;
+  EventRng rng{(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)N, C.key0, C.key1};
+  const u32x4 b0 = rng.block(0);
+
+  // colour ordering and helicities
+  uint64_t A;
+  if (C.in_order) {
+    A = 0;
+#pragma unroll
+    for (int t = 1; t < N; ++t) {
+      // a leg index outside 1..N-1 is clamped so that malformed input never addresses
+      // outside the event's arrays
+      const uint32_t l = C.in_order[i * N + t];
+      A |= (uint64_t)(l < 1u ? 1u : (l > (uint32_t)(N - 1) ? (uint32_t)(N - 1) : l)) << (4 * (t - 1));
+    }
+  } else if (C.random_order) {
+    A = shuffle_order<N>(rng);
+  } else {
+    A = identity_order<N>();
+  }
+  ev.leg[0] = 0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) ev.leg[t] = nib(A, t - 1);
+  ev.hel = C.in_hel ? C.in_hel[i] : (b0.v[2] & ((1u << N) - 1u));
+
+  // parton fractions
+  double sqrt_shat;
+  if (C.use_pdf) {
+    if (C.in_x) {
+      ev.x1 = C.in_x[2 * i];
+      ev.x2 = C.in_x[2 * i + 1];
+    } else {
+      ev.x1 = pdf_sample(u01(b0.v[0]), C.pdf);
+      ev.x2 = pdf_sample(u01(b0.v[1]), C.pdf);
+    }
+    ev.shat = ev.x1 * ev.x2 * C.sqrt_s * C.sqrt_s;
+    sqrt_shat = sqrt(ev.shat);
+  } else {
+    ev.x1 = ev.x2 = 1.0;
+    ev.shat = C.sqrt_s * C.sqrt_s;
+    sqrt_shat = C.sqrt_s;
+  }
+
+  // RAMBO in position order: raw q for outgoing legs, then the conformal map
+  double q[N][4];
+  double Q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const uint32_t j = ev.leg[t];
+    const bool out = j >= 2u;
+    const uint32_t pidx = out ? j - 2u : 0u;
+    double r[4];
+    if (C.in_u) {
+      const double* u = C.in_u + (i * NF + pidx) * 4;
+      r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+    } else {
+      const u32x4 w = rng.block(1u + pidx);
+      r[0] = u01(w.v[0]); r[1] = u01(w.v[1]); r[2] = u01(w.v[2]); r[3] = u01(w.v[3]);
+    }
+    rambo_q(r[0], r[1], r[2], r[3], q[t]);
+    if (out) {
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) Q[mu] += q[t][mu];
+      if (C.out.uniforms) {
+        double* uo = C.out.uniforms + (i * NF + pidx) * 4;
+        uo[0] = r[0]; uo[1] = r[1]; uo[2] = r[2]; uo[3] = r[3];
+      }
+    }
+  }
+  RamboMap map;
+  map.init(Q, sqrt_shat);
+  const double rr = 2.0 * sqrt(ev.x1 * ev.x2);
+  const double ch = (ev.x1 + ev.x2) / rr, sh = (ev.x1 - ev.x2) / rr;
+  const double e1 = 0.5 * C.sqrt_s * ev.x1, e2 = 0.5 * C.sqrt_s * ev.x2;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    const uint32_t j = ev.leg[t];
+    double pc[4];
+    map.apply(q[t], pc);  // harmless for beam positions, overwritten below
+    double pl[4] = {pc[0] * ch + pc[3] * sh, pc[1], pc[2], pc[3] * ch + pc[0] * sh};
+    if (j == 0u) {
+      pl[0] = e1; pl[1] = 0.0; pl[2] = 0.0; pl[3] = e1;
+      pc[0] = 0.5 * sqrt_shat; pc[1] = 0.0; pc[2] = 0.0; pc[3] = 0.5 * sqrt_shat;
+    } else if (j == 1u) {
+      pl[0] = e2; pl[1] = 0.0; pl[2] = 0.0; pl[3] = -e2;
+      pc[0] = 0.5 * sqrt_shat; pc[1] = 0.0; pc[2] = 0.0; pc[3] = -0.5 * sqrt_shat;
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      ev.p[t][mu] = pl[mu];
+      ev.pc[t][mu] = pc[mu];
+    }
+  }
+  if (C.out.hel) C.out.hel[i] = ev.hel;
+  if (C.out.order) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) C.out.order[i * N + t] = (uint8_t)ev.leg[t];
+  }
+  if (C.out.x12) {
+    C.out.x12[2 * i] = ev.x1;
+    C.out.x12[2 * i + 1] = ev.x2;
+  }
+  if (C.out.momenta) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      double* mo = C.out.momenta + (i * N + ev.leg[t]) * 4;
+      mo[0] = ev.p[t][0]; mo[1] = ev.p[t][1]; mo[2] = ev.p[t][2]; mo[3] = ev.p[t][3];
+    }
+  }
+}
+
+// Jet cuts and observables (Sec. 3, Sec. 4) on the outgoing legs.
+template <int N>
+__device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, double& ht, double& rmin) {
+  double pt[N], eta[N], phi[N];
+  bool ok = true;
+  ht = 0.0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double* p = ev.p[t];
+    pt[t] = sqrt(p[1] * p[1] + p[2] * p[2]);
+    eta[t] = asinh(p[3] / pt[t]);
+    phi[t] = atan2(p[2], p[1]);
+    const bool out = ev.leg[t] >= 2u;
+    if (out) {
+      ht += pt[t];
+      ok = ok && (pt[t] > C.pt_min) && (fabs(eta[t]) < C.eta_max);
+    }
+  }
+  double dr2min = 1e300;
+  const double pi = 3.14159265358979323846;
+  static_for<1, N>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    static_for<t + 1, N>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      double dphi = fabs(phi[t] - phi[u]);
+      dphi = dphi > pi ? 2.0 * pi - dphi : dphi;
+      const double deta = eta[t] - eta[u];
+      const double d2 = deta * deta + dphi * dphi;
+      const bool both = (ev.leg[t] >= 2u) && (ev.leg[u] >= 2u);
+      dr2min = both ? fmin(dr2min, d2) : dr2min;
+    });
+  });
+  rmin = sqrt(dr2min);
+  return ok && (dr2min > C.dr_min * C.dr_min);
+}
+
+// |A(sigma;h)|^2 from position-ordered physical momenta.  Momenta are scaled by the power
+// of two 2^-ex nearest below half their summed energy (exact in binary floating point),
+// and |A|^2(k) = 2^(2 ex (4-N)) |A|^2(2^-ex k).
+template <int N, typename T>
+__device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const uint32_t (&leg)[N], uint32_t hel) {
+  double esum = 0.0;
+#pragma unroll
+  for (int t = 0; t < N; ++t) esum += fabs(p[t][0]);
+  const int ex = ilogb(0.5 * esum);
+  const double sc = ldexp(1.0, -ex);
+  double k[N - 1][4];
+  cv4<T> src[N - 1];
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double sg = leg[t] < 2u ? -sc : sc;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) k[t - 1][mu] = sg * p[t][mu];
+    src[t - 1] = polarisation<T>(p[t], (hel >> leg[t]) & 1u);
+  }
+  const cv4<T> e0 = polarisation<T>(p[0], (hel >> leg[0]) & 1u);
+  double mr, mi;
+  bg_amplitude<N - 1, T>(k, src, e0, mr, mi);
+  return ldexp(mr * mr + mi * mi, 2 * ex * (4 - N) - (N - 2));
+}
+
+// Compensated (sum w, sum w^2) of a workgroup of up to 256 lanes, in a fixed tree order;
+// thread 0 stores (s, c, s2, c2) to dst.
+__device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst) {
+  __shared__ double red[4][4];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    CSum ow{__shfl_down(w.s, off), __shfl_down(w.c, off)};
+    CSum ow2{__shfl_down(w2.s, off), __shfl_down(w2.c, off)};
+    w = cs_add(w, ow);
+    w2 = cs_add(w2, ow2);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave][0] = w.s; red[wave][1] = w.c; red[wave][2] = w2.s; red[wave][3] = w2.c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    CSum a{red[0][0], red[0][1]}, b{red[0][2], red[0][3]};
+    const int nw = (int)(blockDim.x >> 6);
+    for (int v = 1; v < nw; ++v) {
+      a = cs_add(a, CSum{red[v][0], red[v][1]});
+      b = cs_add(b, CSum{red[v][2], red[v][3]});
+    }
+    dst[0] = a.s; dst[1] = a.c; dst[2] = b.s; dst[3] = b.c;
+  }
+}
+
+// One event: draws -> kinematics -> cuts -> |A|^2 -> weight; writes outputs; returns w.
+template <int N, typename T>
+__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i) {
+  EventKin<N> ev;
+  build_event<N>(C, i, ev);
+  double ht, rmin;
+  const bool pass = cuts<N>(C, ev, ht, rmin);
+  // |A|^2 is Lorentz invariant: evaluated in the partonic centre-of-mass frame
+  const double a2 = ordered_amp2<N, T>(ev.pc, ev.leg, ev.hel);
+  double sp = 1.0;
+#pragma unroll
+  for (int k = 0; k < (N > 5 ? N - 5 : 5 - N); ++k) sp *= ev.shat;
+  if (N < 5) sp = 1.0 / sp;
+  const double w = pass ? C.wconst * sp * a2 : 0.0;
+  if (C.out.weight) C.out.weight[i] = w;
+  if (C.out.amp2) C.out.amp2[i] = a2;
+  if (C.out.pass) C.out.pass[i] = pass ? 1 : 0;
+  if (C.out.obs) {
+    C.out.obs[2 * i] = ht;
+    C.out.obs[2 * i + 1] = rmin;
+  }
+  return w;
+}
+
+// Single-class generation: one event per lane, one compensated partial per workgroup.
+// Launch: blockDim.x in {64, 128, 192, 256}, one event per lane; partials may be NULL.
+template <int N, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate(GenClass C, double* partials) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double w = 0.0;
+  if (i < C.count) w = generate_one<N, T>(C, i);
+  if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
+}
+
+// |A|^2 from given momenta (bg_amp2): momenta [count][N][4] physical, gathered in colour order.
+template <int N, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_amp2(int64_t count, const double* __restrict__ mom,
+                                                const uint32_t* __restrict__ hel,
+                                                const uint8_t* __restrict__ order,
+                                                double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double p[N][4];
+  uint32_t leg[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    const uint32_t l = order[i * N + t];
+    leg[t] = l < (uint32_t)N ? l : (uint32_t)(N - 1);  // malformed input stays in bounds
+    const double* q = mom + (i * N + leg[t]) * 4;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) p[t][mu] = q[mu];
+  }
+  out[i] = ordered_amp2<N, T>(p, leg, hel[i]);
+}
+
+}  // namespace bgk

@@ -1,0 +1,42 @@
+// Host-visible launch table: one entry per (multiplicity, precision), filled by the
+// per-multiplicity translation units (bg_inst.hip compiled with BG_N = 4..12).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bg_params.hpp"
+
+namespace bgk {
+
+struct GradArgs {
+  int64_t count;
+  double sqrt_s;
+  int32_t use_pdf;
+  double pdf_a;
+  int32_t pdf_b;
+  const double* u;
+  const double* x12;
+  const uint32_t* hel;
+  const uint8_t* order;
+  const double* gout;
+  double* grad_u;
+  double* grad_x;
+  double* logw;
+  double log_const;  // log of the event-independent factors of w_int
+};
+
+using GenerateFn = hipError_t (*)(const GenClass& C, double* partials, int block, hipStream_t s);
+using Amp2Fn = hipError_t (*)(int64_t count, const double* mom, const uint32_t* hel, const uint8_t* order,
+                              double* out, int block, hipStream_t s);
+using GradFn = hipError_t (*)(const GradArgs& G, int block, hipStream_t s);
+
+struct Launchers {
+  GenerateFn generate;
+  Amp2Fn amp2;
+  GradFn grad;
+};
+
+hipError_t launch_finalize(const double* partials, int64_t nparts, double* acc, hipStream_t s);
+
+}  // namespace bgk

@@ -1,0 +1,40 @@
+// Kernel-side parameter blocks, filled by the host layer from bg_config / bg_inputs /
+// bg_outputs (see include/bg.h for the meaning and layout of every array).
+#pragma once
+
+#include <stdint.h>
+
+#include "bg_device.hpp"
+
+namespace bgk {
+
+struct OutPtrs {
+  double* weight;
+  double* amp2;
+  double* obs;
+  uint8_t* pass;
+  double* momenta;
+  uint32_t* hel;
+  uint8_t* order;
+  double* x12;
+  double* uniforms;
+};
+
+// One event class of a generation launch.
+struct GenClass {
+  int64_t count;
+  uint64_t first_event;
+  uint32_t key0, key1;
+  int32_t use_pdf, random_order;
+  double sqrt_s;              // collider sqrt(S), or the fixed sqrt(s_hat) without PDF
+  double pt_min, eta_max, dr_min;
+  double wconst;              // event-independent weight factor (pb GeV^(2(5-n)))
+  PdfParams pdf;
+  const double* in_u;
+  const double* in_x;
+  const uint32_t* in_hel;
+  const uint8_t* in_order;
+  OutPtrs out;
+};
+
+}  // namespace bgk

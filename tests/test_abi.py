@@ -1,0 +1,66 @@
+"""Host-side checks of the C-ABI that need no GPU: every function declared in
+include/bg.h is exported by libbg.so, and argument errors are reported before any
+device work is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1002_3446_amd", "libbg.so")
+HDR = os.path.join(ROOT, "include", "bg.h")
+
+need_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libbg.so not built")
+
+
+def declared():
+    text = open(HDR).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(bg_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_entry_points():
+    assert {"bg_generate", "bg_amp2", "bg_amp2_grad", "bg_strerror", "bg_version",
+            "bg_set_launch", "bg_get_launch"} <= set(declared())
+
+
+@need_lib
+def test_all_declared_symbols_exported():
+    lib = ctypes.CDLL(LIB)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+@need_lib
+def test_host_error_paths():
+    from paper_1002_3446_amd import bg
+    lib = bg.raw()
+    assert bg.version() >= 10000
+    assert bg.strerror(bg.BG_ENOTSUP).startswith("unsupported")
+    c = bg.config(3)
+    counts = (ctypes.c_int64 * 1)(10)
+    outs = (bg.BgOutputs * 1)()
+    assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_ENOTSUP
+    c = bg.config(8, prec=16)
+    assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_ENOTSUP
+    c = bg.config(8)
+    c.reserved = 1
+    assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_EINVAL
+    c = bg.config(8, pt_min=0.0)            # tau_min would be 0: the density is not integrable
+    assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_EINVAL
+    c = bg.config(8, pdf_a=-2.0, pdf_b=5)   # a + k + 1 = 0 at k = 1
+    assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_EINVAL
+    neg = (ctypes.c_int64 * 1)(-1)
+    assert lib.bg_generate(ctypes.byref(bg.config(8)), 1, neg, None, outs, None) == bg.BG_EINVAL
+    assert lib.bg_generate(None, 1, counts, None, outs, None) == bg.BG_EINVAL
+    assert lib.bg_generate(ctypes.byref(bg.config(8)), 0, counts, None, outs, None) == bg.BG_EINVAL
+    assert lib.bg_amp2(13, 64, 5, None, None, None, None, None) == bg.BG_ENOTSUP
+    assert lib.bg_amp2(8, 64, -1, None, None, None, None, None) == bg.BG_EINVAL
+    assert lib.bg_amp2(8, 64, 0, None, None, None, None, None) == bg.BG_OK
+    assert lib.bg_amp2(8, 64, 4, None, None, None, None, None) == bg.BG_EINVAL
+    assert lib.bg_amp2_grad(None, 4, *([None] * 10)) == bg.BG_EINVAL
+    assert lib.bg_set_launch(8, 32, 96, 1) == bg.BG_EINVAL
+    assert lib.bg_set_launch(8, 32, 128, 0) == bg.BG_EINVAL
+    assert lib.bg_set_launch(2, 32, 128, 1) == bg.BG_ENOTSUP
+    b, k = ctypes.c_int(), ctypes.c_int()
+    assert lib.bg_get_launch(8, 32, ctypes.byref(b), ctypes.byref(k)) == bg.BG_OK and b.value in (64, 128, 192, 256)

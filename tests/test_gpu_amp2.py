@@ -1,0 +1,68 @@
+"""GPU parity of bg_amp2 (recursion + closure on given momenta) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import event
+from paper_1002_3446_amd import inputs
+from tests.parity import check_amp2_fp64, fp32_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def make_points(n, N, seed, rs=1000.0):
+    u = inputs.rambo_uniforms(seed, N, n).reshape(N, n - 2, 4)
+    cfg = event.config(n=n, use_pdf=0, sqrt_s=rs)
+    mom, _ = event.kinematics(cfg, u, None)
+    return mom, inputs.helicity_words(seed, N, n), inputs.orderings(seed, N, n)
+
+
+def run_gpu(bg, n, prec, mom, hel, order):
+    m = torch.tensor(mom, device="cuda")
+    h = torch.tensor(hel.astype(np.int64), device="cuda").to(torch.int32)
+    o = torch.tensor(order, device="cuda")
+    out = bg.amp2(n, prec, m, h, o)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9, 10, 11, 12])
+def test_amp2_fp64_parity(gpu_lib, n):
+    N = 8 * 256 + 37            # several workgroups and a ragged tail
+    mom, hel, order = make_points(n, N, 100 + n)
+    print(f"amp2 fp64 n={n} N={N}", flush=True)
+    stats = check_amp2_fp64(run_gpu(gpu_lib, n, 64, mom, hel, order), mom, hel, order)
+    print(stats)
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9, 10, 11, 12])
+def test_amp2_fp32_error(gpu_lib, n):
+    N = 2 * 256 + 11
+    mom, hel, order = make_points(n, N, 200 + n)
+    print(f"amp2 fp32 n={n} N={N}", flush=True)
+    rel = fp32_errors(run_gpu(gpu_lib, n, 32, mom, hel, order), mom, hel, order)
+    q = np.quantile(rel, [0.5, 0.9, 0.99])
+    print(f"n={n} fp32 rel err median {q[0]:.2e} p90 {q[1]:.2e} p99 {q[2]:.2e}")
+    assert q[0] <= 1e-4
+
+
+def test_amp2_empty_and_single(gpu_lib):
+    n = 6
+    mom, _, order = make_points(n, 1, 7)
+    hel = np.array([0b100101], dtype=np.uint32)   # three minus, three plus: non-vanishing
+    out = run_gpu(gpu_lib, n, 64, mom, hel, order)
+    ref = event.amp2(mom, hel, order)
+    assert abs(out[0] / ref[0] - 1) < 1e-12
+    z = torch.empty((0, n, 4), dtype=torch.float64, device="cuda")
+    r = gpu_lib.amp2(n, 64, z, torch.empty(0, dtype=torch.int32, device="cuda"),
+                     torch.empty((0, n), dtype=torch.uint8, device="cuda"))
+    assert r.numel() == 0
+
+
+def test_amp2_unsupported(gpu_lib):
+    n = 3
+    z = torch.zeros((4, n, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.BgError) as e:
+        gpu_lib.amp2(n, 64, z, torch.zeros(4, dtype=torch.int32, device="cuda"),
+                     torch.zeros((4, n), dtype=torch.uint8, device="cuda"))
+    assert e.value.status == gpu_lib.BG_ENOTSUP

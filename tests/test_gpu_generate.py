@@ -1,0 +1,212 @@
+"""GPU parity of bg_generate (Philox draws -> x -> RAMBO -> boost -> cuts -> |A|^2 -> weight
+-> compensated sums) against the oracle, event by event, plus determinism and resume."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import event, pdf
+from oracle.weight import neumaier
+from paper_1002_3446_amd import inputs
+from tests.parity import check_amp2_fp64, fp32_errors
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0**-52
+ALL = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12", "uniforms", "acc")
+
+
+def cfg_c0(bg, prec=64, **kw):
+    """n = 5 at fixed sqrt(s_hat) = 1000 GeV, identity colour ordering."""
+    return bg.config(5, prec=prec, sqrt_s=1000.0, use_pdf=0, random_order=0, seed=0xB6000000, **kw)
+
+
+def cfg_c1(bg, n=8, prec=32, seed=0xB6000001, **kw):
+    """gg -> (n-2) g at sqrt(S) = 14 TeV with the synthetic density, random orderings."""
+    return bg.config(n, prec=prec, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=seed, **kw)
+
+
+def oracle_cfg(c):
+    return event.config(n=c.n, sqrt_s=c.sqrt_s, use_pdf=c.use_pdf, pdf_a=c.pdf_a, pdf_b=c.pdf_b,
+                        tau_min=c.tau_min, alpha_s=c.alpha_s, pt_min=c.pt_min, eta_max=c.eta_max,
+                        dr_min=c.dr_min, random_order=c.random_order, seed=c.seed, first_event=c.first_event)
+
+
+def to_np(res):
+    out = {}
+    for k, v in res.items():
+        a = v.cpu().numpy()
+        if k == "hel":
+            a = a.astype(np.int64) & 0xFFFFFFFF
+        out[k] = a
+    return out
+
+
+def x_bound(ocfg, x):
+    """Conditioning of the inverse CDF: |dx| <~ 64 eps Z / f(x)."""
+    if not ocfg["use_pdf"]:
+        return np.zeros_like(x)
+    Z = pdf.norm(ocfg["tau_min"], ocfg["pdf_a"], int(ocfg["pdf_b"]))
+    return 64 * EPS * Z / pdf.density(x, ocfg["pdf_a"], int(ocfg["pdf_b"]))
+
+
+def compare_events(g, o, ocfg, prec):
+    n = ocfg["n"]
+    N = len(o["amp2"])
+    # integer draws: bit-exact
+    assert np.array_equal(g["hel"], o["hel"].astype(np.int64))
+    assert np.array_equal(g["order"], o["order"])
+    assert np.array_equal(g["uniforms"].reshape(N, n - 2, 4), o["rho"])
+    # parton fractions within the sampler's conditioning
+    dx = np.abs(g["x12"] - o["x12"])
+    assert np.all(dx <= 1e-14 * o["x12"] + x_bound(ocfg, o["x12"]))
+    xrel = (x_bound(ocfg, o["x12"]) / o["x12"]).sum(1)
+    # momenta relative to the event's energy scale
+    escale = o["mom"][:, :, 0].sum(1)
+    dm = np.abs(g["momenta"] - o["mom"]).reshape(N, -1).max(1) / escale
+    assert np.all(dm <= 1e-12 + 4 * xrel), dm.max()
+    # cut decisions agree except for events within rounding of a threshold
+    flip = g["pass"].astype(bool) != o["pass_"]
+    assert np.all(o["margin"][flip] < 1e-9), o["margin"][flip]
+    same = ~flip
+    ok = same & o["pass_"]
+    assert np.allclose(g["obs"][:, 0], o["ht"], rtol=1e-12 + 4 * xrel.max())
+    both = np.isfinite(o["rmin"])
+    assert np.allclose(g["obs"][both, 1], o["rmin"][both], rtol=1e-11 + 4 * xrel.max())
+    extra = 2 * n * xrel
+    if prec == 64:
+        stats = check_amp2_fp64(g["amp2"], o["mom_cm"], o["hel"], o["order"], extra_rel=extra)
+    else:
+        rel = fp32_errors(g["amp2"], o["mom_cm"], o["hel"], o["order"])
+        stats = dict(median=float(np.median(rel)), p99=float(np.quantile(rel, 0.99)))
+        assert stats["median"] <= 1e-4
+    # weights: zero exactly when failing; otherwise weight / |A|^2 (flux, phase-space volume,
+    # colour, density and unit factors) agrees with the oracle's product formula
+    assert np.all(g["weight"][~g["pass"].astype(bool)] == 0.0)
+    sel = ok & (o["amp2"] > 0) & (g["amp2"] > 0)
+    fac = (g["weight"][sel] / g["amp2"][sel]) / (o["weight"][sel] / o["amp2"][sel])
+    assert np.all(np.abs(fac - 1) <= 1e-13 + 2 * n * xrel[sel]), np.abs(fac - 1).max()
+    return stats
+
+
+def test_c0_all_events_fp64(gpu_lib):
+    """n = 5, 65536 events, FP64: every event against the oracle."""
+    c = cfg_c0(gpu_lib)
+    N = 65536
+    print("generate c0 n=5 fp64 N=65536", flush=True)
+    g = to_np(gpu_lib.generate(c, N, outputs=ALL))
+    oc = oracle_cfg(c)
+    o = event.generate(oc, np.arange(N))
+    stats = compare_events(g, o, oc, 64)
+    print(stats)
+    # compensated totals within the per-event agreement plus Higham's bound
+    s_ref, c_ref = neumaier(o["weight"])
+    tot = g["acc"][0] + g["acc"][1]
+    exact_gpu = math.fsum(g["weight"].tolist())
+    assert abs(tot - exact_gpu) <= 2 * EPS * np.abs(g["weight"]).sum()
+    assert abs(tot - (s_ref + c_ref)) <= 1e-11 * np.abs(o["weight"]).sum()
+    s2 = math.fsum((g["weight"] ** 2).tolist())
+    assert abs(g["acc"][2] + g["acc"][3] - s2) <= 2 * EPS * s2
+
+
+@pytest.mark.parametrize("n,prec", [(8, 64), (8, 32), (6, 64), (12, 64), (12, 32), (4, 64), (10, 32)])
+def test_pdf_events(gpu_lib, n, prec):
+    """Synthetic-density events with random orderings, several workgroups and a ragged tail."""
+    c = cfg_c1(gpu_lib, n=n, prec=prec, first_event=12345)
+    N = 4 * 256 + 77
+    print(f"generate pdf n={n} prec={prec} N={N}", flush=True)
+    g = to_np(gpu_lib.generate(c, N, outputs=ALL))
+    oc = oracle_cfg(c)
+    oc["tau_min"] = pdf.tau_min(n, 20.0, 14000.0)
+    o = event.generate(oc, 12345 + np.arange(N))
+    print(compare_events(g, o, oc, prec))
+
+
+def test_given_inputs(gpu_lib):
+    """With caller-supplied uniforms, x1, x2, helicities and orderings the inverse-CDF
+    conditioning drops out: |A|^2 meets the FP64 rules without any widening."""
+    n, N = 8, 1500
+    c = cfg_c1(gpu_lib, n=n, prec=64)
+    u = inputs.rambo_uniforms(5, N, n)
+    x = inputs.x_fractions(5, N, pdf.tau_min(n, 20.0, 14000.0))
+    hel = inputs.helicity_words(5, N, n)
+    order = inputs.orderings(5, N, n)
+    ins = dict(uniforms=torch.tensor(u, device="cuda"), x12=torch.tensor(x, device="cuda"),
+               hel=torch.tensor(hel.astype(np.int64), device="cuda").to(torch.int32),
+               order=torch.tensor(order, device="cuda"))
+    g = to_np(gpu_lib.generate(c, N, inputs=ins, outputs=ALL))
+    oc = oracle_cfg(c)
+    mom, s_hat, mom_cm = event.kinematics(oc, u.reshape(N, n - 2, 4), x, cm=True)
+    assert np.all(np.abs(g["momenta"] - mom).reshape(N, -1).max(1) <= 1e-12 * mom[:, :, 0].sum(1))
+    stats = check_amp2_fp64(g["amp2"], mom_cm, hel, order)
+    print(stats)
+    assert np.array_equal(g["x12"], x) and np.array_equal(g["uniforms"], u)
+
+
+def test_determinism_split_and_shape(gpu_lib):
+    """Per-event outputs are a pure function of the event index: two runs, a split run and a
+    different workgroup size agree bitwise; totals agree within the compensated bound."""
+    n, N = 7, 5000
+    c = cfg_c1(gpu_lib, n=n, prec=32)
+    a = to_np(gpu_lib.generate(c, N, outputs=ALL))
+    b = to_np(gpu_lib.generate(c, N, outputs=ALL))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    c1 = cfg_c1(gpu_lib, n=n, prec=32)
+    c2 = cfg_c1(gpu_lib, n=n, prec=32, first_event=1234)
+    p1 = to_np(gpu_lib.generate(c1, 1234, outputs=ALL))
+    p2 = to_np(gpu_lib.generate(c2, N - 1234, outputs=ALL))
+    for k in ("weight", "amp2", "momenta", "hel", "order", "x12", "pass"):
+        assert np.array_equal(np.concatenate([p1[k], p2[k]]), a[k]), k
+    old = gpu_lib.get_launch(n, 32)
+    try:
+        gpu_lib.set_launch(n, 32, 64, 1)
+        d = to_np(gpu_lib.generate(c, N, outputs=ALL))
+    finally:
+        gpu_lib.set_launch(n, 32, 0, 0)
+    assert gpu_lib.get_launch(n, 32) == old
+    for k in ("weight", "amp2", "momenta", "pass", "obs"):
+        assert np.array_equal(d[k], a[k]), k
+    tot = lambda r: r["acc"][0] + r["acc"][1]
+    sabs = np.abs(a["weight"]).sum()
+    assert abs(tot(d) - tot(a)) <= 4 * EPS * sabs
+    assert abs((tot(p1) + tot(p2)) - tot(a)) <= 4 * EPS * sabs
+
+
+def test_mixed_classes_match_single(gpu_lib):
+    cfgs = [cfg_c1(gpu_lib, n=n, prec=32, seed=77 + n) for n in (4, 6, 9)]
+    counts = [3000, 2000, 700]
+    mixed = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=ALL)]
+    for c, N, m in zip(cfgs, counts, mixed):
+        s = to_np(gpu_lib.generate(c, N, outputs=ALL))
+        for k in ("weight", "amp2", "pass", "hel", "order"):
+            assert np.array_equal(m[k], s[k]), k
+        assert abs((m["acc"][0] + m["acc"][1]) - (s["acc"][0] + s["acc"][1])) <= 4 * EPS * np.abs(s["weight"]).sum()
+
+
+def test_full_size_sampled(gpu_lib):
+    """gg -> 6g, 2^24 events, FP32 recursion (the benchmark configuration): sampled events
+    against the oracle, and the compensated total against the exact sum of the weights."""
+    c = cfg_c1(gpu_lib, n=8, prec=32)
+    N = 1 << 24
+    print("generate n=8 fp32 N=2^24", flush=True)
+    r = gpu_lib.generate(c, N, outputs=("weight", "amp2", "pass", "x12", "acc"))
+    torch.cuda.synchronize()
+    w = r["weight"].cpu().numpy()
+    acc = r["acc"].cpu().numpy()
+    exact = math.fsum(w.tolist())
+    assert abs(acc[0] + acc[1] - exact) <= 2 * EPS * np.abs(w).sum()
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([[0, 1, N - 2, N - 1], rng.integers(0, N, 400)]))
+    oc = oracle_cfg(c)
+    o = event.generate(oc, idx)
+    amp = r["amp2"].cpu().numpy()[idx]
+    ps = r["pass"].cpu().numpy()[idx].astype(bool)
+    x12 = r["x12"].cpu().numpy()[idx]
+    assert np.all(np.abs(x12 - o["x12"]) <= 1e-14 * o["x12"] + x_bound(oc, o["x12"]))
+    flip = ps != o["pass_"]
+    assert np.all(o["margin"][flip] < 1e-9)
+    rel = fp32_errors(amp, o["mom_cm"], o["hel"], o["order"])
+    print("n=8 fp32 sampled rel err quantiles", np.quantile(rel, [0.5, 0.9, 0.99]))
+    assert np.median(rel) <= 1e-4
