@@ -136,7 +136,18 @@ def main():
     ap.add_argument("--events", type=int, default=1 << 24)
     ap.add_argument("--no-extras", action="store_true", help="main line only (used under profilers)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scales HBM counters)")
     a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        src = torch.ones(a.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4}), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); events are independent, "
               "so N GPUs would run disjoint Philox event ranges and add their compensated sums.", file=sys.stderr)
