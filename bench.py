@@ -104,6 +104,32 @@ def run_steps(bg, torch, cfg, N, steps, warmup, outputs):
     return wall, [a.elapsed_time(b) for a, b in evs], out
 
 
+def adjoint_rate(bg, torch, N=1 << 20, steps=5):
+    """Forward + backward of log w_int through the torch Function (gg -> 6g, FP32), on
+    phase-space points the GPU draws first (untimed)."""
+    from paper_1002_3446_amd.autograd import log_weight
+    n = 8
+    cfg = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000004)
+    d = bg.generate(cfg, N, outputs=("uniforms", "x12", "hel", "order"))
+    u = d["uniforms"].requires_grad_(True)
+    x = d["x12"].requires_grad_(True)
+    evs = []
+    for s in range(steps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        u.grad = None
+        x.grad = None
+        a.record()
+        lw = log_weight(u, x, cfg, d["hel"], d["order"])
+        lw.sum().backward()
+        b.record()
+        if s > 0:
+            evs.append((a, b))
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+    return {"n8_fwd_adjoint_fp32_events_per_s": N / (ms * 1e-3), "n8_fwd_adjoint_ms_per_2^20": ms}
+
+
 def live_helicities(hel, n, torch):
     """Mask of helicity words with at least two of each helicity (non-vanishing amplitudes)."""
     bits = (hel.unsqueeze(1) >> torch.arange(n, device=hel.device, dtype=hel.dtype)) & 1
@@ -226,6 +252,7 @@ def main():
         rel = ((r32["amp2"] - b64).abs() / b64.abs())[live_helicities(r32["hel"], 12, torch)]
         q = torch.quantile(rel.float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
         extras["n12_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
+        extras.update(adjoint_rate(bg, torch))
         line["extras"] = extras
 
     if not a.no_cpu:

@@ -88,6 +88,8 @@ typedef struct {
   double *uniforms;  /* [N][4(n-2)] RAMBO uniforms used */
   double *acc;       /* [4] sum w, its compensation, sum w^2, its compensation; the call's
                         compensated totals are ADDED (caller zeroes before the first call) */
+  double *logw;      /* [N] log w_int: the log integrand weight of bg_amp2_grad (no cut step
+                        function, no sampling density); -inf when |A|^2 = 0 */
 } bg_outputs;
 
 /* Generate events of ncfg classes in one launch (Sec. 3; mixed multiplicities when
@@ -111,13 +113,15 @@ int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
  *   log w_int = log f(x1) + log f(x2) - log(2 s_hat) + log V_{n-2}(s_hat)
  *               + log(colour, helicity and ordering factors) + log |A|^2,
  * with respect to the RAMBO uniforms and x1, x2, by a hand-written adjoint of
- * closure, recursion, helicity vectors, boost and RAMBO.  The forward pass is
- * recomputed inside the kernel.
+ * closure, recursion, helicity vectors and RAMBO (|A|^2 is evaluated on the partonic
+ * centre-of-mass momenta, so the longitudinal boost drops out).  The forward pass is
+ * recomputed inside the kernel; log w_int matches bg_outputs.logw of bg_generate.
  * cfg: host pointer (n, prec, sqrt_s, use_pdf, pdf_a, pdf_b, alpha_s are used);
  * uniforms [N][4(n-2)], x12 [N][2] (ignored unless use_pdf), hel [N], order [N][n];
  * gout [N] (dL/dlog w, may be NULL = all ones); grad_u [N][4(n-2)], grad_x [N][2]
  * (zeros when use_pdf = 0) receive gout * d log w_int; logw [N] optional.
- * Events with |A|^2 = 0 get log w = -inf and zero gradients. */
+ * Events with |A|^2 = 0 get log w = -inf and zero gradients.
+ * Supported for n = 4..10 (BG_ENOTSUP for n = 11, 12). */
 int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const double *x12,
                  const uint32_t *hel, const uint8_t *order, const double *gout,
                  double *grad_u, double *grad_x, double *logw, void *stream);

@@ -37,7 +37,7 @@ class BgInputs(ctypes.Structure):
                 ("order", ctypes.c_void_p)]
 
 
-OUTPUT_FIELDS = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12", "uniforms", "acc")
+OUTPUT_FIELDS = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12", "uniforms", "acc", "logw")
 
 
 class BgOutputs(ctypes.Structure):
@@ -48,7 +48,7 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 _lib.bg_generate.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int, _i64p, ctypes.POINTER(BgInputs),
                              ctypes.POINTER(BgOutputs), ctypes.c_void_p]
 _lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 5
-_lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 10
+_lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 9
 _lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
 _lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.bg_strerror.restype = ctypes.c_char_p
@@ -113,6 +113,7 @@ _OUT_SPEC = {  # name -> (dtype, shape given N and n)
     "x12": (torch.float64, lambda N, n: (N, 2)),
     "uniforms": (torch.float64, lambda N, n: (N, 4 * (n - 2))),
     "acc": (torch.float64, lambda N, n: (4,)),
+    "logw": (torch.float64, lambda N, n: (N,)),
 }
 
 

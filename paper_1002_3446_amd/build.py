@@ -34,7 +34,8 @@ def _compile(src: str, obj: str, defines: list[str]) -> str:
     return obj
 
 
-KINDS = (0, 1)  # 0 generate, 1 amp2
+KINDS = (0, 1, 2)  # 0 generate, 1 amp2, 2 gradient
+GRAD_MAX_N = 10    # the fully unrolled adjoint of n = 11, 12 would need 4-8x the register file
 
 
 def units_for(ns, precs=(32, 64), kinds=KINDS):
@@ -43,6 +44,8 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
     for n in ns:
         for p in precs:
             for k in kinds:
+                if k == 2 and n > GRAD_MAX_N:
+                    continue
                 obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}.o")
                 units.append((os.path.join(CSRC, "bg_inst.hip"), obj,
                               [f"-DBG_N={n}", f"-DBG_PREC={p}", f"-DBG_KIND={k}"], n * (2 if p == 64 else 1)))
@@ -51,13 +54,31 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
     return units
 
 
-def build(jobs: int | None = None, verbose: bool = True, ns=range(4, 13)) -> str:
-    """Compiles every unit for the multiplicities ns and links libbg.so."""
+def _newest_source() -> float:
+    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(PKG, "..", "include", "bg.h")]
+    return max(os.path.getmtime(f) for f in srcs)
+
+
+def build(jobs: int | None = None, verbose: bool = True, ns=range(4, 13), incremental: bool = False) -> str:
+    """Compiles every unit for the multiplicities ns and links libbg.so.  incremental=True
+    keeps objects newer than every source (developer convenience; the default rebuilds all)."""
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     units = units_for(list(ns))
+    if incremental:
+        newest = _newest_source()
+        done = [u for u in units if os.path.exists(u[1]) and os.path.getmtime(u[1]) > newest]
+        units_todo = [u for u in units if u not in done]
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units_todo))
+        objs = [u[1] for u in units]
+        return _link(objs, verbose)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units))
+    return _link(objs, verbose)
+
+
+def _link(objs, verbose) -> str:
     tmp = LIB + ".tmp"
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                        capture_output=True, text=True)
@@ -74,5 +95,6 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--ns", type=str, default="4,5,6,7,8,9,10,11,12",
                     help="comma-separated multiplicities to build (others report BG_ENOTSUP)")
+    ap.add_argument("--incremental", action="store_true", help="reuse objects newer than every source")
     a = ap.parse_args()
-    build(a.jobs, ns=[int(x) for x in a.ns.split(",")])
+    build(a.jobs, ns=[int(x) for x in a.ns.split(",")], incremental=a.incremental)

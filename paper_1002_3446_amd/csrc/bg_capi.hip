@@ -127,7 +127,8 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
     P.usplit = (std::pow(P.xsplit, c.pdf_a + 1.0) * psplit - P.Ftau) / P.Z;
     ratio = P.Z * P.Z;
   }
-  G.wconst = ratio * std::exp(log_weight_const(c.n, c.alpha_s));
+  G.log_const = log_weight_const(c.n, c.alpha_s);
+  G.wconst = ratio * std::exp(G.log_const);
   if (in) {
     G.in_u = in->uniforms;
     G.in_x = in->x12;
@@ -144,6 +145,7 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
     G.out.order = out->order;
     G.out.x12 = out->x12;
     G.out.uniforms = out->uniforms;
+    G.out.logw = out->logw;
   }
   return BG_OK;
 }

@@ -382,14 +382,13 @@ __device__ __forceinline__ void span_vertex(const double (&k)[L][4], const cv4<T
   }
 }
 
-// k: FP64 all-outgoing momenta of the L recursion legs (any common power-of-two scale);
-// src: their sources; eps0: the closing leg's polarisation.  Returns m = eps0 . V.
+// Forward recursion: fills every stored current J and span scalar S, and returns the
+// undivided bracket sum V of the full span [0..L-1].
 template <int L, typename T>
-__device__ __forceinline__ void bg_amplitude(const double (&k)[L][4], const cv4<T> (&src)[L],
-                                             const cv4<T>& eps0, double& m_re, double& m_im) {
+__device__ __forceinline__ void bg_forward(const double (&k)[L][4], const cv4<T> (&src)[L],
+                                           cv4<T> (&J)[Spans<L>::count], T (&Sr)[Spans<L>::count],
+                                           T (&Si)[Spans<L>::count], cv4<T>& Vfull) {
   using SP = Spans<L>;
-  cv4<T> J[SP::count];
-  T Sr[SP::count], Si[SP::count];
   static_for<0, L>([&](auto ac) { J[decltype(ac)::value] = src[decltype(ac)::value]; });
   static_for<2, L>([&](auto lc) {
     constexpr int len = decltype(lc)::value;
@@ -409,11 +408,22 @@ __device__ __forceinline__ void bg_amplitude(const double (&k)[L][4], const cv4<
       Si[s] = si;
     });
   });
-  // the full span: amputated, contracted with the closing polarisation (Eq. 3.6)
-  cv4<T> V;
+  // the full span: amputated (Eq. 3.6), never divided by its vanishing K^2
   T sr, si;
   double Kd[4];
-  span_vertex<L, 0, L - 1, T>(k, J, Sr, Si, V, sr, si, Kd);
+  span_vertex<L, 0, L - 1, T>(k, J, Sr, Si, Vfull, sr, si, Kd);
+}
+
+// k: FP64 all-outgoing momenta of the L recursion legs (any common power-of-two scale);
+// src: their sources; eps0: the closing leg's polarisation.  Returns m = eps0 . V.
+template <int L, typename T>
+__device__ __forceinline__ void bg_amplitude(const double (&k)[L][4], const cv4<T> (&src)[L],
+                                             const cv4<T>& eps0, double& m_re, double& m_im) {
+  using SP = Spans<L>;
+  cv4<T> J[SP::count];
+  T Sr[SP::count], Si[SP::count];
+  cv4<T> V;
+  bg_forward<L, T>(k, src, J, Sr, Si, V);
   T mr, mi;
   cdot(eps0, V, mr, mi);
   m_re = double(mr);

@@ -1,6 +1,7 @@
 // Instantiates one kernel kind (BG_KIND: 0 generate, 1 amp2, 2 gradient) of one
 // multiplicity (BG_N, 4..12) and recursion precision (BG_PREC, 32 or 64), and exports its
 // launcher through a host function resolved by the C-ABI layer.
+#include "bg_adjoint.hpp"
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
 
@@ -32,6 +33,12 @@ hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const d
                                                           hipStream_t s) {
   const int64_t nb = (count + block - 1) / block;
   hipLaunchKernelGGL((k_amp2<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
+  return hipGetLastError();
+}
+#elif BG_KIND == 2
+hipError_t BG_NAME(launch_grad_n, BG_N, BG_PREC, BG_KIND)(const GradArgs& G, int block, hipStream_t s) {
+  const int64_t nb = (G.count + block - 1) / block;
+  hipLaunchKernelGGL((k_grad<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, G);
   return hipGetLastError();
 }
 #endif

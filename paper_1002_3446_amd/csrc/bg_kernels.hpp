@@ -243,6 +243,11 @@ __device__ __forceinline__ double generate_one(const GenClass& C, int64_t i) {
     C.out.obs[2 * i] = ht;
     C.out.obs[2 * i + 1] = rmin;
   }
+  if (C.out.logw) {
+    double lw = log(a2) + (N - 5) * log(ev.shat) + C.log_const;
+    if (C.use_pdf) lw += C.pdf.a * (log(ev.x1) + log(ev.x2)) + C.pdf.b * (log1p(-ev.x1) + log1p(-ev.x2));
+    C.out.logw[i] = a2 > 0.0 ? lw : -INFINITY;
+  }
   return w;
 }
 

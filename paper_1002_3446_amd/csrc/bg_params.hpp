@@ -18,6 +18,7 @@ struct OutPtrs {
   uint8_t* order;
   double* x12;
   double* uniforms;
+  double* logw;
 };
 
 // One event class of a generation launch.
@@ -29,6 +30,7 @@ struct GenClass {
   double sqrt_s;              // collider sqrt(S), or the fixed sqrt(s_hat) without PDF
   double pt_min, eta_max, dr_min;
   double wconst;              // event-independent weight factor (pb GeV^(2(5-n)))
+  double log_const;           // log of the event-independent factors of w_int
   PdfParams pdf;
   const double* in_u;
   const double* in_x;
