@@ -104,6 +104,37 @@ def run_steps(bg, torch, cfg, N, steps, warmup, outputs):
     return wall, [a.elapsed_time(b) for a, b in evs], out
 
 
+def mixed_rate(bg, torch):
+    """n = 4..12 with 2^(26-n) events each (8,372,224 events), FP32, one persistent launch,
+    against the same classes launched one after another."""
+    ns = list(range(4, 13))
+    cfgs = [bg.config(n, prec=32, seed=0xB6000003 + n) for n in ns]
+    counts = [1 << (26 - n) for n in ns]
+    outputs = ("weight", "amp2", "obs", "pass", "acc")
+    outs = bg.generate(cfgs, counts, outputs=outputs)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_mixed = timed(lambda: bg.generate(cfgs, counts, outputs=outputs, out_tensors=outs))
+    per_n = {}
+    for c, N, o in zip(cfgs, counts, outs):
+        per_n[c.n] = timed(lambda: bg.generate(c, N, outputs=outputs, out_tensors=[o]))
+    total = sum(counts)
+    return {"mixed_n4_12_fp32_events_per_s": total / (ms_mixed * 1e-3), "mixed_n4_12_ms": ms_mixed,
+            "mixed_n4_12_sequential_ms": sum(per_n.values()),
+            "single_class_fp32_events_per_s": {str(n): counts[i] / (per_n[n] * 1e-3) for i, n in enumerate(ns)}}
+
+
 def adjoint_rate(bg, torch, N=1 << 20, steps=5):
     """Forward + backward of log w_int through the torch Function (gg -> 6g, FP32), on
     phase-space points the GPU draws first (untimed)."""
@@ -253,6 +284,7 @@ def main():
         q = torch.quantile(rel.float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
         extras["n12_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
         extras.update(adjoint_rate(bg, torch))
+        extras.update(mixed_rate(bg, torch))
         line["extras"] = extras
 
     if not a.no_cpu:

@@ -92,8 +92,9 @@ typedef struct {
                         function, no sampling density); -inf when |A|^2 = 0 */
 } bg_outputs;
 
-/* Generate events of ncfg classes in one launch (Sec. 3; mixed multiplicities when
- * ncfg > 1).  Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
+/* Generate events of ncfg classes (Sec. 3).  One class: one launch of that multiplicity's
+ * kernel.  Several classes (mixed multiplicities): one persistent launch per recursion
+ * precision present, whose workgroups take tiles (largest n first) from a shared queue.  Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
  * event i of a class is a pure function of (seed, first_event + i, n) and of
  * ins[k] when given, so split runs reproduce an unsplit run event by event.
  * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
@@ -126,12 +127,13 @@ int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const 
                  const uint32_t *hel, const uint8_t *order, const double *gout,
                  double *grad_u, double *grad_x, double *logw, void *stream);
 
-/* Launch shape for one (n, prec) class: threads per workgroup (64, 128 or 256) and
- * workgroups per compute unit for the persistent multi-class launch (1..8).
- * The autotuner writes these; 0 restores the built-in default.  Affects speed only:
- * per-event outputs are identical for every shape.  Errors: BG_ENOTSUP, BG_EINVAL. */
-int bg_set_launch(int n, int prec, int block, int blocks_per_cu);
-int bg_get_launch(int n, int prec, int *block, int *blocks_per_cu);
+/* Launch shape for one (n, prec) class: threads per workgroup (64, 128, 192 or 256) and
+ * events per lane in one tile of the persistent multi-class launch (1..64; a tile holds
+ * block * tile_iters events).  The autotuner writes these; (0, 0) restores the built-in
+ * default.  Affects speed only: per-event outputs are identical for every shape, totals
+ * agree within the compensated-sum bound.  Errors: BG_ENOTSUP, BG_EINVAL. */
+int bg_set_launch(int n, int prec, int block, int tile_iters);
+int bg_get_launch(int n, int prec, int *block, int *tile_iters);
 
 /* Static message for a status code. */
 const char *bg_strerror(int status);

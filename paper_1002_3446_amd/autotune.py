@@ -1,0 +1,102 @@
+"""Launch-shape autotuner for libbg (needs a GPU).
+
+For every multiplicity n and recursion precision it times single-class bg_generate with
+64, 128 and 256 threads per workgroup and keeps the fastest; then, on the mixed workload
+(n = 4..12 with 2^(26-n) events each, one persistent launch), it tunes each class's tile
+length (events per lane per tile) by coordinate search.  The result is written to
+autotune.json next to this file, which the binding applies on import.
+
+Usage: python -m paper_1002_3446_amd.autotune [--prec 32] [--out PATH] [--scale S]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import torch
+
+from . import bg
+
+NS = list(range(4, 13))
+
+
+def _time(fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def mixed_workload(prec, scale=0):
+    cfgs = [bg.config(n, prec=prec, seed=0xB6000003 + n) for n in NS]
+    counts = [1 << (26 - n - scale) for n in NS]
+    return cfgs, counts
+
+
+def tune(prec=32, scale=0, log=print):
+    shapes = {}
+    for n in NS:
+        N = 1 << max(20 - scale, 26 - n - scale)
+        cfg = bg.config(n, prec=prec, seed=0xB6000003 + n)
+        out = bg.generate(cfg, N, outputs=("weight", "acc"))
+        best = None
+        for block in (64, 128, 256):
+            bg.set_launch(n, prec, block, bg.get_launch(n, prec)[1] or 1)
+            t = _time(lambda: bg.generate(cfg, N, outputs=("weight", "acc"), out_tensors=[out]))
+            log(f"n={n} prec={prec} block={block}: {t:.3f} ms for {N} events")
+            if best is None or t < best[0]:
+                best = (t, block)
+        shapes[n] = [best[1], bg.get_launch(n, prec)[1]]
+        bg.set_launch(n, prec, shapes[n][0], shapes[n][1])
+    cfgs, counts = mixed_workload(prec, scale)
+    outs = bg.generate(cfgs, counts, outputs=("weight", "acc"))
+    run = lambda: bg.generate(cfgs, counts, outputs=("weight", "acc"), out_tensors=outs)
+    base = _time(run)
+    log(f"mixed launch, default tiles: {base:.3f} ms")
+    for n in NS:
+        best = (base, shapes[n][1])
+        for it in (1, 2, 4, 8, 16):
+            bg.set_launch(n, prec, shapes[n][0], it)
+            t = _time(run)
+            if t < best[0] * 0.995:
+                best = (t, it)
+        shapes[n][1] = best[1]
+        bg.set_launch(n, prec, shapes[n][0], best[1])
+        base = best[0]
+        log(f"n={n}: tile_iters={best[1]} -> mixed {base:.3f} ms")
+    return [dict(n=n, prec=prec, block=b, tile_iters=i) for n, (b, i) in shapes.items()], base
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--prec", type=int, default=32)
+    ap.add_argument("--scale", type=int, default=0, help="shrink every workload by 2^scale")
+    ap.add_argument("--out", default=bg.TUNING_PATH)
+    a = ap.parse_args()
+    t0 = time.time()
+    for n in NS:
+        bg.set_launch(n, a.prec, 0, 0)   # start from the built-in defaults
+    shapes, ms = tune(a.prec, a.scale)
+    doc = {"device": torch.cuda.get_device_name(0), "mixed_ms": ms, "tuned_in_s": time.time() - t0,
+           "shapes": shapes}
+    if os.path.exists(a.out):
+        old = json.load(open(a.out))
+        keep = [e for e in old.get("shapes", []) if e["prec"] != a.prec]
+        doc["shapes"] = keep + shapes
+    with open(a.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(json.dumps(doc))
+
+
+if __name__ == "__main__":
+    main()

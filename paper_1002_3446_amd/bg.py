@@ -191,14 +191,32 @@ def amp2_grad(cfg: BgConfig, u, x12, hel, order, gout=None, want_logw=True):
     return gu, gx, lw
 
 
-def set_launch(n: int, prec: int, block: int, blocks_per_cu: int):
-    _check("bg_set_launch", _lib.bg_set_launch(n, prec, block, blocks_per_cu))
+def set_launch(n: int, prec: int, block: int, tile_iters: int):
+    """Threads per workgroup and events per lane in a multi-class tile; (0, 0) = default."""
+    _check("bg_set_launch", _lib.bg_set_launch(n, prec, block, tile_iters))
 
 
 def get_launch(n: int, prec: int):
     b, c = ctypes.c_int(), ctypes.c_int()
     _check("bg_get_launch", _lib.bg_get_launch(n, prec, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+TUNING_PATH = os.path.join(_HERE, "autotune.json")
+
+
+def load_tuning(path: str = TUNING_PATH) -> int:
+    """Applies launch shapes written by paper_1002_3446_amd.autotune; returns how many."""
+    import json
+    if not os.path.exists(path):
+        return 0
+    entries = json.load(open(path)).get("shapes", [])
+    for e in entries:
+        set_launch(int(e["n"]), int(e["prec"]), int(e["block"]), int(e["tile_iters"]))
+    return len(entries)
+
+
+load_tuning()
 
 
 def raw():

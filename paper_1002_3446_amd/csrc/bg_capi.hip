@@ -2,9 +2,11 @@
 // stream-ordered workspace for the compensated reduction, and kernel dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "../../include/bg.h"
 #include "bg_launch.hpp"
@@ -38,19 +40,39 @@ const Launchers* table(int n, int prec) {
   return &t[n - 4][prec == 32 ? 0 : 1];
 }
 
-// launch shapes per (n, prec): threads per workgroup and workgroups per CU
+// launch shapes per (n, prec): threads per workgroup, and events per lane in one tile of
+// the multi-class launch (cheap small-n events get longer tiles)
 struct Shape {
-  int block, per_cu;
+  int block, tile_iters;
 };
 std::mutex g_shape_mu;
 Shape g_shape[13][2];
-const Shape kDefaultShape{256, 1};
+
+Shape default_shape(int n) {
+  static const int iters[13] = {0, 0, 0, 0, 8, 6, 4, 3, 2, 1, 1, 1, 1};
+  return Shape{256, iters[n]};
+}
 
 Shape shape_of(int n, int prec) {
   std::lock_guard<std::mutex> lk(g_shape_mu);
   Shape s = g_shape[n][prec == 32 ? 0 : 1];
-  if (s.block == 0) s = kDefaultShape;
+  if (s.block == 0) s = default_shape(n);
   return s;
+}
+
+// compute units of the current device (cached per device)
+int cu_count() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cache[dev] = c;
+  }
+  return cache[dev];
 }
 
 constexpr double kPi = 3.14159265358979323846;
@@ -152,6 +174,61 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
 
 int from_hip(hipError_t e) { return e == hipSuccess ? BG_OK : BG_EHIP; }
 
+// Persistent multi-class launch over the classes ks (all of recursion precision prec):
+// tile list ordered by decreasing n, class table and tiles copied to a stream-ordered
+// workspace together with the zeroed tile counter.
+int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* outs, std::vector<int> ks, int prec,
+                   hipStream_t s) {
+  std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return cfgs[a].n > cfgs[b].n; });
+  std::vector<MultiClass> mcs(ks.size());
+  std::vector<Tile> tiles;
+  int block = 256;
+  for (size_t c = 0; c < ks.size(); ++c) {
+    const int k = ks[c];
+    const Shape sh = shape_of(cfgs[k].n, prec);
+    block = std::min(block, sh.block);
+  }
+  for (size_t c = 0; c < ks.size(); ++c) {
+    const int k = ks[c];
+    const Shape sh = shape_of(cfgs[k].n, prec);
+    const int64_t tile = (int64_t)block * sh.tile_iters;
+    MultiClass& m = mcs[c];
+    std::memset(&m, 0, sizeof(m));
+    m.C = G[k];
+    m.n = cfgs[k].n;
+    m.acc = outs[k].acc;
+    m.tile_begin = (int)tiles.size();
+    for (int64_t f = 0; f < G[k].count; f += tile)
+      tiles.push_back(Tile{f, (int32_t)std::min<int64_t>(tile, G[k].count - f), (int32_t)c});
+    m.tile_end = (int)tiles.size();
+  }
+  if (tiles.empty()) return BG_OK;
+  if (tiles.size() > (size_t)0x7fffffff) return BG_EINVAL;
+  const size_t o_cls = 0;
+  const size_t o_tiles = (o_cls + mcs.size() * sizeof(MultiClass) + 255) & ~size_t(255);
+  const size_t o_ctr = (o_tiles + tiles.size() * sizeof(Tile) + 255) & ~size_t(255);
+  const size_t o_part = o_ctr + 256;
+  const size_t bytes = o_part + tiles.size() * 4 * sizeof(double);
+  std::vector<unsigned char> blob(o_part, 0);  // classes, tiles and a zero counter
+  std::memcpy(blob.data() + o_cls, mcs.data(), mcs.size() * sizeof(MultiClass));
+  std::memcpy(blob.data() + o_tiles, tiles.data(), tiles.size() * sizeof(Tile));
+  unsigned char* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return BG_ENOMEM;
+  }
+  // pageable source: the copy is staged before hipMemcpyAsync returns, so blob may go
+  int st = from_hip(hipMemcpyAsync(ws, blob.data(), o_part, hipMemcpyHostToDevice, s));
+  if (st == BG_OK) {
+    const int grid = cu_count() * (256 / block);
+    auto launch = prec == 32 ? launch_generate_multi_p32 : launch_generate_multi_p64;
+    st = from_hip(launch((const MultiClass*)(ws + o_cls), (int)mcs.size(), (const Tile*)(ws + o_tiles),
+                         (int)tiles.size(), (int*)(ws + o_ctr), (double*)(ws + o_part), grid, block, s));
+  }
+  (void)hipFreeAsync(ws, s);
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -169,25 +246,25 @@ const char* bg_strerror(int status) {
   }
 }
 
-int bg_set_launch(int n, int prec, int block, int blocks_per_cu) {
+int bg_set_launch(int n, int prec, int block, int tile_iters) {
   if (!table(n, prec)) return BG_ENOTSUP;
-  if (block == 0 && blocks_per_cu == 0) {
+  if (block == 0 && tile_iters == 0) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[n][prec == 32 ? 0 : 1] = Shape{0, 0};
     return BG_OK;
   }
-  if (block < 64 || block > 256 || block % 64 != 0 || blocks_per_cu < 1 || blocks_per_cu > 8) return BG_EINVAL;
+  if (block < 64 || block > 256 || block % 64 != 0 || tile_iters < 1 || tile_iters > 64) return BG_EINVAL;
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  g_shape[n][prec == 32 ? 0 : 1] = Shape{block, blocks_per_cu};
+  g_shape[n][prec == 32 ? 0 : 1] = Shape{block, tile_iters};
   return BG_OK;
 }
 
-int bg_get_launch(int n, int prec, int* block, int* blocks_per_cu) {
+int bg_get_launch(int n, int prec, int* block, int* tile_iters) {
   if (!table(n, prec)) return BG_ENOTSUP;
-  if (!block || !blocks_per_cu) return BG_EINVAL;
+  if (!block || !tile_iters) return BG_EINVAL;
   const Shape s = shape_of(n, prec);
   *block = s.block;
-  *blocks_per_cu = s.per_cu;
+  *tile_iters = s.tile_iters;
   return BG_OK;
 }
 
@@ -200,6 +277,18 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
     if (st != BG_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
+  if (ncfg > 1) {
+    // one persistent launch per recursion precision present
+    for (int prec : {32, 64}) {
+      std::vector<int> ks;
+      for (int k = 0; k < ncfg; ++k)
+        if (cfgs[k].prec == prec && G[k].count > 0) ks.push_back(k);
+      if (ks.empty()) continue;
+      const int st = generate_multi(cfgs, G, outs, ks, prec, s);
+      if (st != BG_OK) return st;
+    }
+    return BG_OK;
+  }
   for (int k = 0; k < ncfg; ++k) {
     if (G[k].count == 0) continue;
     const Launchers* L = table(cfgs[k].n, cfgs[k].prec);

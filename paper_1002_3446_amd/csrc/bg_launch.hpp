@@ -39,4 +39,23 @@ struct Launchers {
 
 hipError_t launch_finalize(const double* partials, int64_t nparts, double* acc, hipStream_t s);
 
+// One class of a multi-class launch and one tile of its work list (device-resident).
+struct MultiClass {
+  GenClass C;
+  int32_t n;
+  int32_t tile_begin, tile_end;  // this class's tiles in the list
+  double* acc;
+};
+
+struct Tile {
+  int64_t first;  // first local event index
+  int32_t count;
+  int32_t cls;
+};
+
+hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
+                                     int* counter, double* partials, int grid, int block, hipStream_t s);
+hipError_t launch_generate_multi_p64(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
+                                     int* counter, double* partials, int grid, int block, hipStream_t s);
+
 }  // namespace bgk

@@ -161,7 +161,7 @@ def test_determinism_split_and_shape(gpu_lib):
         assert np.array_equal(np.concatenate([p1[k], p2[k]]), a[k]), k
     old = gpu_lib.get_launch(n, 32)
     try:
-        gpu_lib.set_launch(n, 32, 64, 1)
+        gpu_lib.set_launch(n, 32, 64, 3)
         d = to_np(gpu_lib.generate(c, N, outputs=ALL))
     finally:
         gpu_lib.set_launch(n, 32, 0, 0)
@@ -210,3 +210,32 @@ def test_full_size_sampled(gpu_lib):
     rel = fp32_errors(amp, o["mom_cm"], o["hel"], o["order"])
     print("n=8 fp32 sampled rel err quantiles", np.quantile(rel, [0.5, 0.9, 0.99]))
     assert np.median(rel) <= 1e-4
+
+
+def test_mixed_all_multiplicities(gpu_lib):
+    """n = 4..12 in one persistent launch (event counts 2^(18-n)): per-event outputs equal the
+    single-class kernels' bit for bit, per-class totals within the compensated bound."""
+    ns = list(range(4, 13))
+    cfgs = [cfg_c1(gpu_lib, n=n, prec=32, seed=1000 + n) for n in ns]
+    counts = [1 << (18 - n) for n in ns]
+    print("mixed n=4..12 fp32", flush=True)
+    mixed = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=ALL)]
+    for c, N, m in zip(cfgs, counts, mixed):
+        s = to_np(gpu_lib.generate(c, N, outputs=ALL))
+        for k in ("weight", "amp2", "pass", "hel", "order", "momenta", "obs"):
+            assert np.array_equal(m[k], s[k]), (c.n, k)
+        assert abs((m["acc"][0] + m["acc"][1]) - (s["acc"][0] + s["acc"][1])) <= 4 * EPS * np.abs(s["weight"]).sum()
+
+
+def test_mixed_precisions_and_empty_class(gpu_lib):
+    cfgs = [cfg_c1(gpu_lib, n=6, prec=64, seed=5), cfg_c1(gpu_lib, n=5, prec=32, seed=6),
+            cfg_c1(gpu_lib, n=7, prec=32, seed=7)]
+    counts = [700, 0, 900]
+    mixed = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=ALL)]
+    assert mixed[1]["weight"].size == 0 and np.all(mixed[1]["acc"] == 0)
+    for c, N, m in zip(cfgs, counts, mixed):
+        if N == 0:
+            continue
+        s = to_np(gpu_lib.generate(c, N, outputs=ALL))
+        for k in ("weight", "amp2", "pass"):
+            assert np.array_equal(m[k], s[k]), (c.n, k)
