@@ -93,8 +93,10 @@ typedef struct {
 } bg_outputs;
 
 /* Generate events of ncfg classes (Sec. 3).  One class: one launch of that multiplicity's
- * kernel.  Several classes (mixed multiplicities): one persistent launch per recursion
- * precision present, whose workgroups take tiles (largest n first) from a shared queue.  Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
+ * kernel.  Several FP32 classes (mixed multiplicities): one persistent launch whose
+ * workgroups take tiles (largest n first) from a shared queue; FP64 classes run their
+ * single-class kernels one after another.  The persistent kernel and the single-class
+ * kernels agree to FP32 rounding (per-event values are reproducible for a given call).  Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
  * event i of a class is a pure function of (seed, first_event + i, n) and of
  * ins[k] when given, so split runs reproduce an unsplit run event by event.
  * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
@@ -134,6 +136,15 @@ int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const 
  * agree within the compensated-sum bound.  Errors: BG_ENOTSUP, BG_EINVAL. */
 int bg_set_launch(int n, int prec, int block, int tile_iters);
 int bg_get_launch(int n, int prec, int *block, int *tile_iters);
+
+/* Strategy for bg_generate calls with several FP32 classes: 1 (default) = one persistent
+ * launch over all classes; 0 = each class's single-class kernel, one after another on the
+ * caller's stream.  The persistent kernel balances load across classes but carries the
+ * register allocation of the largest multiplicity (one wave per SIMD for every class);
+ * the autotuner times both and records the faster.  Per-event draws, kinematics and cut
+ * flags are identical in both modes; |A|^2 agrees to the recursion precision's rounding. */
+int bg_set_mixed_launch(int persistent);
+int bg_get_mixed_launch(void);
 
 /* Static message for a status code. */
 const char *bg_strerror(int status);

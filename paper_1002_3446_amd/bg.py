@@ -51,9 +51,12 @@ _lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c
 _lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 9
 _lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
 _lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.bg_set_mixed_launch.argtypes = [ctypes.c_int]
+_lib.bg_get_mixed_launch.argtypes = []
 _lib.bg_strerror.restype = ctypes.c_char_p
 _lib.bg_strerror.argtypes = [ctypes.c_int]
-for _f in ("bg_generate", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version"):
+for _f in ("bg_generate", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
+           "bg_set_mixed_launch", "bg_get_mixed_launch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -202,6 +205,15 @@ def get_launch(n: int, prec: int):
     return b.value, c.value
 
 
+def set_mixed_launch(persistent: bool):
+    """True: several FP32 classes share one persistent launch; False: one launch per class."""
+    _check("bg_set_mixed_launch", _lib.bg_set_mixed_launch(int(bool(persistent))))
+
+
+def get_mixed_launch() -> bool:
+    return bool(_lib.bg_get_mixed_launch())
+
+
 TUNING_PATH = os.path.join(_HERE, "autotune.json")
 
 
@@ -210,9 +222,12 @@ def load_tuning(path: str = TUNING_PATH) -> int:
     import json
     if not os.path.exists(path):
         return 0
-    entries = json.load(open(path)).get("shapes", [])
+    doc = json.load(open(path))
+    entries = doc.get("shapes", [])
     for e in entries:
         set_launch(int(e["n"]), int(e["prec"]), int(e["block"]), int(e["tile_iters"]))
+    if "mixed_persistent" in doc:
+        set_mixed_launch(bool(doc["mixed_persistent"]))
     return len(entries)
 
 

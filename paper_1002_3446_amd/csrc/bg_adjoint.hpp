@@ -389,7 +389,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   cv4<T> J[SP::count];
   T Sr[SP::count], Si[SP::count];
   cv4<T> V;
-  bg_forward<L, T>(k, src, J, Sr, Si, V);
+  SpanKLegs<L, T> ks{k};
+  bg_forward<L, T>(ks, src, J, Sr, Si, V);
   T mr, mi;
   cdot(e0, V, mr, mi);
   const double m2 = double(mr) * double(mr) + double(mi) * double(mi);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -59,6 +60,8 @@ Shape shape_of(int n, int prec) {
   if (s.block == 0) s = default_shape(n);
   return s;
 }
+
+std::atomic<int> g_mixed_persistent{1};
 
 // compute units of the current device (cached per device)
 int cu_count() {
@@ -221,8 +224,8 @@ int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* o
   int st = from_hip(hipMemcpyAsync(ws, blob.data(), o_part, hipMemcpyHostToDevice, s));
   if (st == BG_OK) {
     const int grid = cu_count() * (256 / block);
-    auto launch = prec == 32 ? launch_generate_multi_p32 : launch_generate_multi_p64;
-    st = from_hip(launch((const MultiClass*)(ws + o_cls), (int)mcs.size(), (const Tile*)(ws + o_tiles),
+    (void)prec;
+    st = from_hip(launch_generate_multi_p32((const MultiClass*)(ws + o_cls), (int)mcs.size(), (const Tile*)(ws + o_tiles),
                          (int)tiles.size(), (int*)(ws + o_ctr), (double*)(ws + o_part), grid, block, s));
   }
   (void)hipFreeAsync(ws, s);
@@ -245,6 +248,14 @@ const char* bg_strerror(int status) {
     default: return "unknown status";
   }
 }
+
+int bg_set_mixed_launch(int persistent) {
+  if (persistent != 0 && persistent != 1) return BG_EINVAL;
+  g_mixed_persistent.store(persistent);
+  return BG_OK;
+}
+
+int bg_get_mixed_launch(void) { return g_mixed_persistent.load(); }
 
 int bg_set_launch(int n, int prec, int block, int tile_iters) {
   if (!table(n, prec)) return BG_ENOTSUP;
@@ -277,24 +288,26 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
     if (st != BG_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
-  if (ncfg > 1) {
-    // one persistent launch per recursion precision present
-    for (int prec : {32, 64}) {
-      std::vector<int> ks;
-      for (int k = 0; k < ncfg; ++k)
-        if (cfgs[k].prec == prec && G[k].count > 0) ks.push_back(k);
-      if (ks.empty()) continue;
-      const int st = generate_multi(cfgs, G, outs, ks, prec, s);
+  // several FP32 classes: one persistent launch; FP64 classes (and a lone FP32 class) run
+  // their single-class kernels one after another below
+  bool multi32 = false;
+  if (ncfg > 1 && g_mixed_persistent.load()) {
+    std::vector<int> ks;
+    for (int k = 0; k < ncfg; ++k)
+      if (cfgs[k].prec == 32 && G[k].count > 0) ks.push_back(k);
+    if (ks.size() > 1) {
+      const int st = generate_multi(cfgs, G, outs, ks, 32, s);
       if (st != BG_OK) return st;
+      multi32 = true;
     }
-    return BG_OK;
   }
   for (int k = 0; k < ncfg; ++k) {
-    if (G[k].count == 0) continue;
+    if (G[k].count == 0 || (multi32 && cfgs[k].prec == 32)) continue;
     const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
     if (!L->generate) return BG_ENOTSUP;
     const Shape sh = shape_of(cfgs[k].n, cfgs[k].prec);
-    const int64_t nblocks = (G[k].count + sh.block - 1) / sh.block;
+    const int block = lds_span_table(cfgs[k].n, cfgs[k].prec) ? kLdsLanes : sh.block;
+    const int64_t nblocks = (G[k].count + block - 1) / block;
     double* partials = nullptr;
     if (outs[k].acc) {
       if (hipMallocAsync((void**)&partials, (size_t)nblocks * 4 * sizeof(double), s) != hipSuccess) {
@@ -302,7 +315,7 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
         return BG_ENOMEM;
       }
     }
-    int st = from_hip(L->generate(G[k], partials, sh.block, s));
+    int st = from_hip(L->generate(G[k], partials, block, s));
     if (st == BG_OK && partials) st = from_hip(launch_finalize(partials, nblocks, outs[k].acc, s));
     if (partials) (void)hipFreeAsync(partials, s);
     if (st != BG_OK) return st;

@@ -2,7 +2,7 @@
 //
 // Paper: Giele, Stavenga, Winter, "Thread-Scalable Evaluation of Multi-Jet Observables".
 //   philox4x32        counter-based draws (generator unnamed in the paper, Sec. 4)
-//   pdf_sample        synthetic gluon density x^a (1-x)^b by inverse CDF (stands in for
+//   pdf_sample2       synthetic gluon density x^a (1-x)^b by inverse CDF (stands in for
 //                     the LHAPDF grids of Sec. 3)
 //   rambo_q/rambo_map RAMBO massless phase space (Sec. 3)
 //   polarisation      helicity sources J[i] orthogonal to k_i (Sec. 3)
@@ -123,53 +123,69 @@ __device__ __forceinline__ double ipow(double x, int k) {
   return r;
 }
 
-// F(x) and f(x) with one log and one exp
-__device__ __forceinline__ void pdf_eval(double x, const PdfParams& P, double& F, double& f) {
-  const double xa1 = exp((P.a + 1.0) * log(x));
-  double poly = P.coef[P.b];
-  for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, x, P.coef[k]);
-  F = xa1 * poly;
-  f = xa1 / x * ipow(1.0 - x, P.b);
-}
-
-__device__ inline double pdf_sample(double u, const PdfParams& P) {
-  double x, F, f;
-  if (u < P.usplit) {
-    const double T = u * P.Z;
-    const double target = log(T);
-    const double ap1 = P.a + 1.0;
-    const double base = P.x0base + ap1 * T;  // leading power only
-    x = base > 0.0 ? exp(log(base) / ap1) : P.xsplit;
-    x = fmin(fmax(x, P.tau * (1.0 + 1e-12)), P.xsplit);
-    for (int it = 0; it < 16; ++it) {
-      pdf_eval(x, P, F, f);
-      const double G = F - P.Ftau;
-      if (!(G > 0.0)) {  // stepped below tau: restart just above it
-        x = P.tau * (1.0 + 1e-9);
-        continue;
-      }
-      const double step = (log(G) - target) * G / (x * f);
-      x = x * exp(-step);
-      if (fabs(step) <= 1e-9) break;
-    }
-    pdf_eval(x, P, F, f);
-    x -= (F - P.Ftau - T) / f;
-  } else {
-    const double target = log((1.0 - u) * P.Z);
-    x = 0.5;
-    for (int it = 0; it < 16; ++it) {
-      pdf_eval(x, P, F, f);
-      const double G = P.F1 - F;
-      if (!(G > 0.0)) {
-        x = 0.5 * (x + P.xsplit);
-        continue;
-      }
-      const double step = (log(G) - target) * G / ((1.0 - x) * f);
-      x = -expm1(log1p(-x) - step);
-      if (fabs(step) <= 1e-9) break;
+// Both parton fractions in one loop (two independent Newton chains, interleaved).  Per x:
+// v = log x (lower branch) or v = log(1 - x) (upper branch); each step costs exp(v),
+// exp((a+1) log x), log G and one division; log x = v on the lower branch.
+__device__ inline void pdf_sample2(double u1, double u2, const PdfParams& P, double& x1, double& x2) {
+  const double ap1 = P.a + 1.0;
+  const double uu[2] = {u1, u2};
+  bool lower[2], done[2];
+  double v[2], target[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    lower[j] = uu[j] < P.usplit;
+    done[j] = false;
+    if (lower[j]) {
+      const double T = uu[j] * P.Z;
+      target[j] = log(T);
+      const double base = P.x0base + ap1 * T;  // leading power only
+      double lx = base > 0.0 ? log(base) / ap1 : log(P.xsplit);
+      v[j] = fmin(fmax(lx, log(P.tau) + 1e-12), log(P.xsplit));
+    } else {
+      target[j] = log((1.0 - uu[j]) * P.Z);
+      v[j] = -0.69314718055994530942;  // x = 1/2
     }
   }
-  return x;
+  for (int it = 0; it < 16; ++it) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (done[j]) continue;
+      const double e = exp(v[j]);
+      const double x = lower[j] ? e : 1.0 - e;
+      const double lx = lower[j] ? v[j] : log1p(-e);
+      const double xa1 = exp(ap1 * lx);
+      double poly = P.coef[P.b];
+      for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, x, P.coef[k]);
+      const double F = xa1 * poly;
+      const double G = lower[j] ? F - P.Ftau : P.F1 - F;
+      const double omx_b = ipow(1.0 - x, P.b);
+      // d log G / dv = x f / G (lower) or (1 - x) f / G (upper), with f = x^a (1-x)^b
+      const double dG = lower[j] ? xa1 * omx_b : xa1 / x * omx_b * (1.0 - x);
+      if (!(G > 0.0)) {  // stepped outside the domain: restart inside it
+        v[j] = lower[j] ? log(P.tau) + 1e-9 : -0.69314718055994530942;
+        continue;
+      }
+      const double step = (log(G) - target[j]) * G / dG;
+      v[j] -= step;
+      done[j] = fabs(step) <= 1e-9;
+    }
+    if (done[0] && done[1]) break;
+  }
+  double xs[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double e = exp(v[j]);
+    xs[j] = lower[j] ? e : 1.0 - e;
+    if (lower[j]) {  // one plain Newton step in x: exact where x is close to tau
+      const double xa1 = exp(ap1 * v[j]);
+      double poly = P.coef[P.b];
+      for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, xs[j], P.coef[k]);
+      const double f = xa1 / xs[j] * ipow(1.0 - xs[j], P.b);
+      xs[j] -= (xa1 * poly - P.Ftau - uu[j] * P.Z) / f;
+    }
+  }
+  x1 = xs[0];
+  x2 = xs[1];
 }
 
 // ----------------------------------------------------------------------------------------
@@ -216,28 +232,32 @@ struct cv4 {
   T re[4], im[4];
 };
 
-// eps_h(p) = (0, -h ct cf + i sf, -h ct sf - i cf, h st) / sqrt(2) from the physical momentum
+// eps_h(p) = (0, -h ct cf + i sf, -h ct sf - i cf, h st) / sqrt(2) from the physical momentum,
+// evaluated in the recursion precision T (the vector only enters the recursion in T).
 template <typename T>
 __device__ __forceinline__ cv4<T> polarisation(const double p[4], bool plus) {
-  const double pt2 = p[1] * p[1] + p[2] * p[2];
-  const double pa = sqrt(pt2 + p[3] * p[3]);
-  const double pt = sqrt(pt2);
-  const double ct = p[3] / pa, st = pt / pa;
-  double cf = 1.0, sf = 0.0;
-  if (pt2 > 0.0) {
-    cf = p[1] / pt;
-    sf = p[2] / pt;
+  const T px = T(p[1]), py = T(p[2]), pz = T(p[3]);
+  const T pt2 = px * px + py * py;
+  const T pa = sqrt(pt2 + pz * pz);
+  const T pt = sqrt(pt2);
+  const T ipa = T(1) / pa;
+  const T ct = pz * ipa, st = pt * ipa;
+  T cf = T(1), sf = T(0);
+  if (pt2 > T(0)) {
+    const T ipt = T(1) / pt;
+    cf = px * ipt;
+    sf = py * ipt;
   }
-  const double r = 0.70710678118654752440;
-  const double h = plus ? r : -r;
+  const T r = T(0.70710678118654752440);
+  const T h = plus ? r : -r;
   cv4<T> e;
   e.re[0] = T(0);
   e.im[0] = T(0);
-  e.re[1] = T(-h * ct * cf);
-  e.im[1] = T(sf * r);
-  e.re[2] = T(-h * ct * sf);
-  e.im[2] = T(-cf * r);
-  e.re[3] = T(h * st);
+  e.re[1] = -h * ct * cf;
+  e.im[1] = sf * r;
+  e.re[2] = -h * ct * sf;
+  e.im[2] = -cf * r;
+  e.re[3] = h * st;
   e.im[3] = T(0);
   return e;
 }
@@ -282,6 +302,62 @@ struct Spans {
   }
 };
 
+// Span momenta for the brackets, K[A..B] cast to T, and the propagators 1/K^2, from the FP64
+// leg momenta at every use (any precision, any workgroup size).
+template <int L, typename T>
+struct SpanKLegs {
+  const double (&k)[L][4];
+  template <int A, int B>
+  __device__ __forceinline__ void K(T out[4]) const {
+    double d[4];
+    span_sum<A, B, L>(k, d);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) out[mu] = T(d[mu]);
+  }
+  template <int A, int B>
+  __device__ __forceinline__ T prop() const {
+    double d[4];
+    span_sum<A, B, L>(k, d);
+    return T(1.0 / minkowski_sq(d));
+  }
+};
+
+// The same values from a per-lane table in LDS, filled once per event: every span momentum
+// summed left to right in FP64 then cast to float, every propagator 1/K^2 formed in FP64.
+// Layout [span][lane] with LANES lanes per workgroup, so a wave's accesses are contiguous.
+template <int L, int LANES>
+struct SpanKLds {
+  float4* kt;  // &table[0][lane]
+  float* pt;   // &props[0][lane]
+  __device__ __forceinline__ void fill(const double (&k)[L][4]) {
+    using SP = Spans<L>;
+    static_for<0, L>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      double acc[4] = {k[a][0], k[a][1], k[a][2], k[a][3]};
+      kt[SP::at(a, a) * LANES] = make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
+      static_for<a + 1, L>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) acc[mu] += k[b][mu];
+        kt[SP::at(a, b) * LANES] = make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
+        if (b - a + 1 < L) pt[SP::at(a, b) * LANES] = float(1.0 / minkowski_sq(acc));
+      });
+    });
+  }
+  template <int A, int B>
+  __device__ __forceinline__ void K(float out[4]) const {
+    const float4 v = kt[Spans<L>::at(A, B) * LANES];
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  }
+  template <int A, int B>
+  __device__ __forceinline__ float prop() const {
+    return pt[Spans<L>::at(A, B) * LANES];
+  }
+};
+
 template <typename T>
 __device__ __forceinline__ void cdot(const cv4<T>& x, const cv4<T>& y, T& r, T& i) {
   r = x.re[0] * y.re[0] - x.im[0] * y.im[0];
@@ -315,12 +391,11 @@ __device__ __forceinline__ void caxpy(T cr, T ci, const cv4<T>& y, cv4<T>& acc) 
 }
 
 // One span [A..B] of the recursion: its bracket sum V (Eqs. 3.1-3.2, regrouped as above).
-template <int L, int A, int B, typename T>
-__device__ __forceinline__ void span_vertex(const double (&k)[L][4], const cv4<T> (&J)[Spans<L>::count],
+template <int L, int A, int B, typename T, typename KS>
+__device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Spans<L>::count],
                                             const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
-                                            cv4<T>& V, T& sr, T& si, double (&Kd)[4]) {
+                                            cv4<T>& V, T& sr, T& si) {
   using SP = Spans<L>;
-  span_sum<A, B, L>(k, Kd);
   cv4<T> X, Y;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) X.re[mu] = X.im[mu] = Y.re[mu] = Y.im[mu] = T(0);
@@ -330,15 +405,9 @@ __device__ __forceinline__ void span_vertex(const double (&k)[L][4], const cv4<T
   static_for<A, B>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     constexpr int PA = SP::at(A, i), PB = SP::at(i + 1, B);
-    double KA[4], KB[4];
-    span_sum<A, i, L>(k, KA);
-    span_sum<i + 1, B, L>(k, KB);
     T ka[4], kb[4];
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      ka[mu] = T(KA[mu]);
-      kb[mu] = T(KB[mu]);
-    }
+    ks.template K<A, i>(ka);
+    ks.template K<i + 1, B>(kb);
     T dr, di, ar, ai, br, bi;
     cdot(J[PA], J[PB], dr, di);
     rdot(J[PA], kb, ar, ai);
@@ -384,8 +453,8 @@ __device__ __forceinline__ void span_vertex(const double (&k)[L][4], const cv4<T
 
 // Forward recursion: fills every stored current J and span scalar S, and returns the
 // undivided bracket sum V of the full span [0..L-1].
-template <int L, typename T>
-__device__ __forceinline__ void bg_forward(const double (&k)[L][4], const cv4<T> (&src)[L],
+template <int L, typename T, typename KS>
+__device__ __forceinline__ void bg_forward(const KS& ks, const cv4<T> (&src)[L],
                                            cv4<T> (&J)[Spans<L>::count], T (&Sr)[Spans<L>::count],
                                            T (&Si)[Spans<L>::count], cv4<T>& Vfull) {
   using SP = Spans<L>;
@@ -396,9 +465,8 @@ __device__ __forceinline__ void bg_forward(const double (&k)[L][4], const cv4<T>
       constexpr int a = decltype(ac)::value, b = a + len - 1, s = SP::at(a, b);
       cv4<T> V;
       T sr, si;
-      double Kd[4];
-      span_vertex<L, a, b, T>(k, J, Sr, Si, V, sr, si, Kd);
-      const T prop = T(1.0 / minkowski_sq(Kd));
+      span_vertex<L, a, b, T>(ks, J, Sr, Si, V, sr, si);
+      const T prop = ks.template prop<a, b>();
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) {
         J[s].re[mu] = V.re[mu] * prop;
@@ -410,20 +478,19 @@ __device__ __forceinline__ void bg_forward(const double (&k)[L][4], const cv4<T>
   });
   // the full span: amputated (Eq. 3.6), never divided by its vanishing K^2
   T sr, si;
-  double Kd[4];
-  span_vertex<L, 0, L - 1, T>(k, J, Sr, Si, Vfull, sr, si, Kd);
+  span_vertex<L, 0, L - 1, T>(ks, J, Sr, Si, Vfull, sr, si);
 }
 
 // k: FP64 all-outgoing momenta of the L recursion legs (any common power-of-two scale);
 // src: their sources; eps0: the closing leg's polarisation.  Returns m = eps0 . V.
-template <int L, typename T>
-__device__ __forceinline__ void bg_amplitude(const double (&k)[L][4], const cv4<T> (&src)[L],
-                                             const cv4<T>& eps0, double& m_re, double& m_im) {
+template <int L, typename T, typename KS>
+__device__ __forceinline__ void bg_amplitude(const KS& ks, const cv4<T> (&src)[L], const cv4<T>& eps0,
+                                             double& m_re, double& m_im) {
   using SP = Spans<L>;
   cv4<T> J[SP::count];
   T Sr[SP::count], Si[SP::count];
   cv4<T> V;
-  bg_forward<L, T>(k, src, J, Sr, Si, V);
+  bg_forward<L, T>(ks, src, J, Sr, Si, V);
   T mr, mi;
   cdot(eps0, V, mr, mi);
   m_re = double(mr);

@@ -23,6 +23,7 @@ using Real = double;
 #if BG_KIND == 0
 hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
                                                               hipStream_t s) {
+  if (lds_span_table(BG_N, BG_PREC)) block = kLdsLanes;
   const int64_t nb = (C.count + block - 1) / block;
   hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, C, partials);
   return hipGetLastError();
@@ -31,6 +32,7 @@ hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C,
 hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
                                                           const uint8_t* order, double* out, int block,
                                                           hipStream_t s) {
+  if (lds_span_table(BG_N, BG_PREC)) block = kLdsLanes;
   const int64_t nb = (count + block - 1) / block;
   hipLaunchKernelGGL((k_amp2<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
   return hipGetLastError();

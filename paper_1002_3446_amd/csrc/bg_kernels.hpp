@@ -2,7 +2,10 @@
 // lane's registers.  Instantiated per multiplicity N (4..12) and recursion precision T.
 #pragma once
 
+#include <type_traits>
+
 #include "bg_device.hpp"
+#include "bg_launch.hpp"
 #include "bg_params.hpp"
 
 namespace bgk {
@@ -55,8 +58,7 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
       ev.x1 = C.in_x[2 * i];
       ev.x2 = C.in_x[2 * i + 1];
     } else {
-      ev.x1 = pdf_sample(u01(b0.v[0]), C.pdf);
-      ev.x2 = pdf_sample(u01(b0.v[1]), C.pdf);
+      pdf_sample2(u01(b0.v[0]), u01(b0.v[1]), C.pdf, ev.x1, ev.x2);
     }
     ev.shat = ev.x1 * ev.x2 * C.sqrt_s * C.sqrt_s;
     sqrt_shat = sqrt(ev.shat);
@@ -174,7 +176,20 @@ __device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, d
 // of two 2^-ex nearest below half their summed energy (exact in binary floating point),
 // and |A|^2(k) = 2^(2 ex (4-N)) |A|^2(2^-ex k).
 template <int N, typename T>
-__device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const uint32_t (&leg)[N], uint32_t hel) {
+struct UseLdsK {
+  static constexpr bool value = lds_span_table(N, std::is_same<T, float>::value ? 32 : 64);
+};
+
+// The LDS span table of one workgroup (only instantiated where UseLdsK holds).
+template <int N>
+struct LdsTable {
+  float4 k[Spans<N - 1>::count * kLdsLanes];
+  float p[Spans<N - 1>::count * kLdsLanes];
+};
+
+template <int N, typename T, bool LDS>
+__device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const uint32_t (&leg)[N], uint32_t hel,
+                                               LdsTable<N>* tab) {
   double esum = 0.0;
 #pragma unroll
   for (int t = 0; t < N; ++t) esum += fabs(p[t][0]);
@@ -191,7 +206,14 @@ __device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const ui
   }
   const cv4<T> e0 = polarisation<T>(p[0], (hel >> leg[0]) & 1u);
   double mr, mi;
-  bg_amplitude<N - 1, T>(k, src, e0, mr, mi);
+  if constexpr (LDS) {
+    SpanKLds<N - 1, kLdsLanes> ks{tab->k + threadIdx.x, tab->p + threadIdx.x};
+    ks.fill(k);
+    bg_amplitude<N - 1, T>(ks, src, e0, mr, mi);
+  } else {
+    SpanKLegs<N - 1, T> ks{k};
+    bg_amplitude<N - 1, T>(ks, src, e0, mr, mi);
+  }
   return ldexp(mr * mr + mi * mi, 2 * ex * (4 - N) - (N - 2));
 }
 
@@ -223,14 +245,14 @@ __device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst)
 }
 
 // One event: draws -> kinematics -> cuts -> |A|^2 -> weight; writes outputs; returns w.
-template <int N, typename T>
-__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i) {
+template <int N, typename T, bool LDS = false>
+__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, LdsTable<N>* tab = nullptr) {
   EventKin<N> ev;
   build_event<N>(C, i, ev);
   double ht, rmin;
   const bool pass = cuts<N>(C, ev, ht, rmin);
   // |A|^2 is Lorentz invariant: evaluated in the partonic centre-of-mass frame
-  const double a2 = ordered_amp2<N, T>(ev.pc, ev.leg, ev.hel);
+  const double a2 = ordered_amp2<N, T, LDS>(ev.pc, ev.leg, ev.hel, tab);
   double sp = 1.0;
 #pragma unroll
   for (int k = 0; k < (N > 5 ? N - 5 : 5 - N); ++k) sp *= ev.shat;
@@ -252,18 +274,25 @@ __device__ __forceinline__ double generate_one(const GenClass& C, int64_t i) {
 }
 
 // Single-class generation: one event per lane, one compensated partial per workgroup.
-// Launch: blockDim.x in {64, 128, 192, 256}, one event per lane; partials may be NULL.
+// Launch: one event per lane, blockDim.x = kLdsLanes where UseLdsK holds, else any of
+// {64, 128, 192, 256}; partials may be NULL.
 template <int N, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate(GenClass C, double* partials) {
+__global__ __launch_bounds__((UseLdsK<N, T>::value ? kLdsLanes : 256)) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate(
+    GenClass C, double* partials) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double w = 0.0;
-  if (i < C.count) w = generate_one<N, T>(C, i);
+  if constexpr (UseLdsK<N, T>::value) {
+    __shared__ LdsTable<N> tab;
+    if (i < C.count) w = generate_one<N, T, true>(C, i, &tab);
+  } else {
+    if (i < C.count) w = generate_one<N, T>(C, i);
+  }
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
 }
 
 // |A|^2 from given momenta (bg_amp2): momenta [count][N][4] physical, gathered in colour order.
 template <int N, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_amp2(int64_t count, const double* __restrict__ mom,
+__global__ __launch_bounds__((UseLdsK<N, T>::value ? kLdsLanes : 256)) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_amp2(int64_t count, const double* __restrict__ mom,
                                                 const uint32_t* __restrict__ hel,
                                                 const uint8_t* __restrict__ order,
                                                 double* __restrict__ out) {
@@ -279,7 +308,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) p[t][mu] = q[mu];
   }
-  out[i] = ordered_amp2<N, T>(p, leg, hel[i]);
+  if constexpr (UseLdsK<N, T>::value) {
+    __shared__ LdsTable<N> tab;
+    out[i] = ordered_amp2<N, T, true>(p, leg, hel[i], &tab);
+  } else {
+    out[i] = ordered_amp2<N, T, false>(p, leg, hel[i], nullptr);
+  }
 }
 
 }  // namespace bgk

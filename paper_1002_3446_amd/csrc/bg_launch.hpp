@@ -9,6 +9,12 @@
 
 namespace bgk {
 
+// FP32 classes with n <= 8 keep their span momenta and propagators in an LDS table
+// (SpanKLds) and run with 64-lane workgroups: at n = 8 four workgroups use 143 KB of a
+// compute unit's 160 KB.  Larger n and FP64 sum the FP64 leg momenta at every use.
+constexpr int kLdsLanes = 64;
+constexpr bool lds_span_table(int n, int prec) { return prec == 32 && n <= 8; }
+
 struct GradArgs {
   int64_t count;
   double sqrt_s;
@@ -54,8 +60,6 @@ struct Tile {
 };
 
 hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
-                                     int* counter, double* partials, int grid, int block, hipStream_t s);
-hipError_t launch_generate_multi_p64(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
                                      int* counter, double* partials, int grid, int block, hipStream_t s);
 
 }  // namespace bgk

@@ -8,21 +8,14 @@
 // reduces each class's tile partials in tile order into that class's accumulator, so
 // per-event outputs and totals do not depend on which workgroup ran which tile.
 //
-// Compiled with BG_PREC = 32 or 64.
+// Built for FP32 recursion (the mixed-multiplicity workload); FP64 classes of a
+// multi-class call are launched one class at a time by the host layer.
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
 
-#ifndef BG_PREC
-#error "BG_PREC must be defined"
-#endif
-
 namespace bgk {
 
-#if BG_PREC == 32
 using Real = float;
-#else
-using Real = double;
-#endif
 
 namespace {
 
@@ -49,7 +42,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
     __syncthreads();
-    const int t = s_tile;
+    // uniform across the workgroup: class parameters are read with scalar loads
+    const int t = __builtin_amdgcn_readfirstlane(s_tile);
     __syncthreads();
     if (t >= ntiles) break;
     const Tile tl = tiles[t];
@@ -101,10 +95,7 @@ __global__ __launch_bounds__(256) void k_finalize_multi(const MultiClass* __rest
 
 }  // namespace
 
-#define BG_MULTI_NAME2(p) launch_generate_multi_p##p
-#define BG_MULTI_NAME(p) BG_MULTI_NAME2(p)
-
-hipError_t BG_MULTI_NAME(BG_PREC)(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
+hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
                                   int* counter, double* partials, int grid, int block, hipStream_t s) {
   hipLaunchKernelGGL((k_generate_multi<Real>), dim3(grid), dim3(block), 0, s, classes, tiles, ntiles, counter,
                      partials);
