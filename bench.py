@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (counts packed FP32; this build emits scalar FP32 only)
+PEAK_FP32_SCALAR = 78.6e12  # the same without packed FP32: 256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP64 = 78.6e12    # MI355X vector FP64
 PAPER_N8_EVENTS_PER_S = 1.0 / 3.546e-7   # Table 1 of the paper, NVIDIA Tesla, FP32 (context only)
 
@@ -42,18 +43,17 @@ def flops_plain(n: int) -> int:
 
 
 def flops_executed(n: int) -> int:
-    """Per-event floating-point operations the kernel's recursion executes (fma = 2):
-    per span of length l: FP64 span sum 4(l-1); per split: K updates 8 (4 on the first),
-    complex dot 30, two complex-real dots 28, two complex axpys 64 (+2 negations),
-    (K_A - K_B) 4, its axpy 16, S 2; per pair of splits: dot 30 + axpy 32; 2(l-2) S-terms of 34;
-    V = 2X + Y 16; then propagator 16 or closure dot 30."""
+    """Per-event floating-point operations of the recursion and closure as the kernel
+    executes them (fma = 2; span momenta and propagators come precomputed): per split of a
+    span, complex dot 30, two complex-real dots 28, two complex axpys 64, K_A - K_B 4 and
+    its axpy 16, the span scalar 2 (144); per pair of splits, dot 30 + axpy 32; 2(l-2)
+    span-scalar axpys of 32; V = 2X + Y 16; then the propagator 8, or the closure dot 30."""
     L = n - 1
     tot = 0
     for length in range(2, L + 1):
         spans = L - length + 1
-        s = length - 1
-        per = 4 * (length - 1) + s * 154 - 4 + 62 * comb(length - 1, 2) + 34 * 2 * (length - 2) + 16
-        per += 16 if length < L else 30
+        per = 144 * (length - 1) + 62 * comb(length - 1, 2) + 64 * (length - 2) + 16
+        per += 8 if length < L else 30
         tot += spans * per
     return tot
 
@@ -105,8 +105,8 @@ def run_steps(bg, torch, cfg, N, steps, warmup, outputs):
 
 
 def mixed_rate(bg, torch):
-    """n = 4..12 with 2^(26-n) events each (8,372,224 events), FP32, one persistent launch,
-    against the same classes launched one after another."""
+    """n = 4..12 with 2^(26-n) events each (8,372,224 events), FP32: one persistent launch,
+    one class after another, and classes on concurrent streams; the rate is the fastest."""
     ns = list(range(4, 13))
     cfgs = [bg.config(n, prec=32, seed=0xB6000003 + n) for n in ns]
     counts = [1 << (26 - n) for n in ns]
@@ -126,17 +126,18 @@ def mixed_rate(bg, torch):
         return a.elapsed_time(b) / reps
 
     mode = bg.get_mixed_launch()
-    bg.set_mixed_launch(True)
-    ms_mixed = timed(lambda: bg.generate(cfgs, counts, outputs=outputs, out_tensors=outs))
-    bg.set_mixed_launch(False)
-    ms_per_class = timed(lambda: bg.generate(cfgs, counts, outputs=outputs, out_tensors=outs))
+    ms_modes = {}
+    for name, m in (("persistent", bg.MIXED_PERSISTENT), ("sequential", bg.MIXED_SEQUENTIAL),
+                    ("concurrent", bg.MIXED_CONCURRENT)):
+        bg.set_mixed_launch(m)
+        ms_modes[name] = timed(lambda: bg.generate(cfgs, counts, outputs=outputs, out_tensors=outs))
     bg.set_mixed_launch(mode)
     per_n = {}
     for c, N, o in zip(cfgs, counts, outs):
         per_n[c.n] = timed(lambda: bg.generate(c, N, outputs=outputs, out_tensors=[o]))
     total = sum(counts)
-    return {"mixed_n4_12_fp32_events_per_s": total / (min(ms_mixed, ms_per_class) * 1e-3),
-            "mixed_n4_12_persistent_ms": ms_mixed, "mixed_n4_12_per_class_ms": ms_per_class,
+    return {"mixed_n4_12_fp32_events_per_s": total / (min(ms_modes.values()) * 1e-3),
+            "mixed_n4_12_ms_by_mode": ms_modes, "mixed_n4_12_tuned_mode": mode,
             "mixed_n4_12_sum_of_single_ms": sum(per_n.values()),
             "single_class_fp32_events_per_s": {str(n): counts[i] / (per_n[n] * 1e-3) for i, n in enumerate(ns)}}
 
@@ -165,6 +166,30 @@ def adjoint_rate(bg, torch, N=1 << 20, steps=5):
     torch.cuda.synchronize()
     ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
     return {"n8_fwd_adjoint_fp32_events_per_s": N / (ms * 1e-3), "n8_fwd_adjoint_ms_per_2^20": ms}
+
+
+def recursion_rate(bg, torch, n=8, N=1 << 22, reps=5):
+    """bg_amp2 alone (helicity sources, recursion, closure; FP32) on phase-space points the
+    generator draws first (untimed): the recursion kernel's own FLOP rate."""
+    cfg = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000005)
+    d = bg.generate(cfg, N, outputs=("momenta", "hel", "order"))
+    out = bg.amp2(n, 32, d["momenta"], d["hel"], d["order"])
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        bg.amp2(n, 32, d["momenta"], d["hel"], d["order"], out=out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    fp, fe = flops_plain(n), flops_executed(n)
+    return {"kernel": f"k_amp2<{n},float>", "events": N, "launch_ms": ms, "events_per_s": N / (ms * 1e-3),
+            "achieved_plain_tflops": fp * N / (ms * 1e-3) / 1e12, "frac_plain": fp * N / (ms * 1e-3) / PEAK_FP32,
+            "achieved_executed_tflops": fe * N / (ms * 1e-3) / 1e12,
+            "frac_executed": fe * N / (ms * 1e-3) / PEAK_FP32,
+            "frac_executed_of_scalar_fp32": fe * N / (ms * 1e-3) / PEAK_FP32_SCALAR,
+            "hbm_bytes_per_event": 8 * 4 * n + 4 + n + 8}
 
 
 def live_helicities(hel, n, torch):
@@ -289,6 +314,7 @@ def main():
         rel = ((r32["amp2"] - b64).abs() / b64.abs())[live_helicities(r32["hel"], 12, torch)]
         q = torch.quantile(rel.float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
         extras["n12_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
+        line["recursion_kernel"] = recursion_rate(bg, torch)
         extras.update(adjoint_rate(bg, torch))
         extras.update(mixed_rate(bg, torch))
         line["extras"] = extras

@@ -93,10 +93,12 @@ typedef struct {
 } bg_outputs;
 
 /* Generate events of ncfg classes (Sec. 3).  One class: one launch of that multiplicity's
- * kernel.  Several FP32 classes (mixed multiplicities): one persistent launch whose
- * workgroups take tiles (largest n first) from a shared queue; FP64 classes run their
- * single-class kernels one after another.  The persistent kernel and the single-class
- * kernels agree to FP32 rounding (per-event values are reproducible for a given call).  Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
+ * kernel (after a small setup launch that tabulates the inverse CDF of the parton density
+ * when x1, x2 are sampled).  Several classes (mixed multiplicities): as chosen by
+ * bg_set_mixed_launch, either one after another, or the FP32 classes in one persistent
+ * launch whose workgroups take tiles (largest n first) from a shared queue, or side by side
+ * on concurrent streams.  Per-event values are reproducible for a given call and mode.
+ * Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
  * event i of a class is a pure function of (seed, first_event + i, n) and of
  * ins[k] when given, so split runs reproduce an unsplit run event by event.
  * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
@@ -137,13 +139,19 @@ int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const 
 int bg_set_launch(int n, int prec, int block, int tile_iters);
 int bg_get_launch(int n, int prec, int *block, int *tile_iters);
 
-/* Strategy for bg_generate calls with several FP32 classes: 1 (default) = one persistent
- * launch over all classes; 0 = each class's single-class kernel, one after another on the
- * caller's stream.  The persistent kernel balances load across classes but carries the
- * register allocation of the largest multiplicity (one wave per SIMD for every class);
- * the autotuner times both and records the faster.  Per-event draws, kinematics and cut
- * flags are identical in both modes; |A|^2 agrees to the recursion precision's rounding. */
-int bg_set_mixed_launch(int persistent);
+/* Strategy for bg_generate calls with several classes (process-wide setting):
+ *   0  each class's single-class kernel, one after another on the caller's stream;
+ *   1  (default) the FP32 classes in one persistent launch (FP64 classes as in 0);
+ *   2  the classes' single-class kernels on up to four library-owned side streams (created
+ *      once per device at default priority, kept until the process ends), forked from and
+ *      joined back into the caller's stream with events, so that classes too small to
+ *      fill the GPU run side by side.
+ * The persistent kernel balances load across classes but carries the register allocation
+ * of the largest multiplicity (one wave per SIMD for every class); the autotuner times
+ * the three and records the fastest.  Per-event draws, kinematics and cut flags are
+ * identical in every mode; |A|^2 agrees to the recursion precision's rounding (modes 0
+ * and 2 run the same kernels and agree exactly).  Errors: BG_EINVAL for another value. */
+int bg_set_mixed_launch(int mode);
 int bg_get_mixed_launch(void);
 
 /* Static message for a status code. */

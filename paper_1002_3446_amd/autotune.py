@@ -3,8 +3,9 @@
 For every multiplicity n and recursion precision it times single-class bg_generate with
 64, 128 and 256 threads per workgroup and keeps the fastest; then, on the mixed workload
 (n = 4..12 with 2^(26-n) events each, one persistent launch), it tunes each class's tile
-length (events per lane per tile) by coordinate search, and finally records whether the
-persistent launch or one launch per class is faster for that workload.  The result is written to
+length (events per lane per tile) by coordinate search, and finally records which of the
+three strategies for several classes (one after another, one persistent launch, classes on
+concurrent streams) is fastest for that workload.  The result is written to
 autotune.json next to this file, which the binding applies on import.
 
 Usage: python -m paper_1002_3446_amd.autotune [--prec 32] [--out PATH] [--scale S]
@@ -75,11 +76,13 @@ def tune(prec=32, scale=0, log=print):
         bg.set_launch(n, prec, shapes[n][0], best[1])
         base = best[0]
         log(f"n={n}: tile_iters={best[1]} -> mixed {base:.3f} ms")
-    bg.set_mixed_launch(False)
-    per_class = _time(run)
-    bg.set_mixed_launch(True)
-    log(f"mixed workload: persistent {base:.3f} ms, one launch per class {per_class:.3f} ms")
-    return [dict(n=n, prec=prec, block=b, tile_iters=i) for n, (b, i) in shapes.items()], base, per_class
+    modes = {"persistent": base}
+    for name, m in (("sequential", bg.MIXED_SEQUENTIAL), ("concurrent", bg.MIXED_CONCURRENT)):
+        bg.set_mixed_launch(m)
+        modes[name] = _time(run)
+    bg.set_mixed_launch(bg.MIXED_PERSISTENT)
+    log("mixed workload: " + ", ".join(f"{k} {v:.3f} ms" for k, v in modes.items()))
+    return [dict(n=n, prec=prec, block=b, tile_iters=i) for n, (b, i) in shapes.items()], modes
 
 
 def main():
@@ -91,10 +94,12 @@ def main():
     t0 = time.time()
     for n in NS:
         bg.set_launch(n, a.prec, 0, 0)   # start from the built-in defaults
-    bg.set_mixed_launch(True)
-    shapes, ms, ms_per_class = tune(a.prec, a.scale)
-    doc = {"device": torch.cuda.get_device_name(0), "mixed_persistent_ms": ms, "mixed_per_class_ms": ms_per_class,
-           "mixed_persistent": ms <= ms_per_class, "tuned_in_s": time.time() - t0, "shapes": shapes}
+    bg.set_mixed_launch(bg.MIXED_PERSISTENT)
+    shapes, modes = tune(a.prec, a.scale)
+    ids = {"sequential": bg.MIXED_SEQUENTIAL, "persistent": bg.MIXED_PERSISTENT, "concurrent": bg.MIXED_CONCURRENT}
+    best = min(modes, key=modes.get)
+    doc = {"device": torch.cuda.get_device_name(0), "mixed_ms": modes, "mixed_mode": ids[best],
+           "mixed_mode_name": best, "tuned_in_s": time.time() - t0, "shapes": shapes}
     if os.path.exists(a.out):
         old = json.load(open(a.out))
         keep = [e for e in old.get("shapes", []) if e["prec"] != a.prec]

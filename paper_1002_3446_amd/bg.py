@@ -205,13 +205,18 @@ def get_launch(n: int, prec: int):
     return b.value, c.value
 
 
-def set_mixed_launch(persistent: bool):
-    """True: several FP32 classes share one persistent launch; False: one launch per class."""
-    _check("bg_set_mixed_launch", _lib.bg_set_mixed_launch(int(bool(persistent))))
+MIXED_SEQUENTIAL, MIXED_PERSISTENT, MIXED_CONCURRENT = 0, 1, 2
 
 
-def get_mixed_launch() -> bool:
-    return bool(_lib.bg_get_mixed_launch())
+def set_mixed_launch(mode: int):
+    """Strategy for calls with several classes: MIXED_SEQUENTIAL (one class after another),
+    MIXED_PERSISTENT (FP32 classes in one persistent launch) or MIXED_CONCURRENT (classes
+    on concurrent side streams)."""
+    _check("bg_set_mixed_launch", _lib.bg_set_mixed_launch(int(mode)))
+
+
+def get_mixed_launch() -> int:
+    return int(_lib.bg_get_mixed_launch())
 
 
 TUNING_PATH = os.path.join(_HERE, "autotune.json")
@@ -226,8 +231,8 @@ def load_tuning(path: str = TUNING_PATH) -> int:
     entries = doc.get("shapes", [])
     for e in entries:
         set_launch(int(e["n"]), int(e["prec"]), int(e["block"]), int(e["tile_iters"]))
-    if "mixed_persistent" in doc:
-        set_mixed_launch(bool(doc["mixed_persistent"]))
+    if "mixed_mode" in doc:
+        set_mixed_launch(int(doc["mixed_mode"]))
     return len(entries)
 
 

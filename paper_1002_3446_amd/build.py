@@ -40,7 +40,8 @@ GRAD_MAX_N = 10    # the fully unrolled adjoint of n = 11, 12 would need 4-8x th
 
 def units_for(ns, precs=(32, 64), kinds=KINDS):
     units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"), [], 0),
-             (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0)]
+             (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0),
+             (os.path.join(CSRC, "bg_pdf.hip"), os.path.join(OUT_DIR, "bg_pdf.o"), [], 0)]
     # the persistent multi-class kernel holds every multiplicity: start it first
     units.append((os.path.join(CSRC, "bg_multi.hip"), os.path.join(OUT_DIR, "bg_multi_p32.o"), [], 1000))
     for n in ns:

@@ -28,8 +28,8 @@ __device__ __forceinline__ void cdot_adj(const cv4<T>& y, T dbr, T dbi, cv4<T>& 
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const T g = gsign<T>(mu);
-    xb.re[mu] += g * (y.re[mu] * dbr + y.im[mu] * dbi);
-    xb.im[mu] += g * (y.re[mu] * dbi - y.im[mu] * dbr);
+    xb.re[mu] = fmac(g * y.im[mu], dbi, fmac(g * y.re[mu], dbr, xb.re[mu]));
+    xb.im[mu] = fmac(-g * y.im[mu], dbr, fmac(g * y.re[mu], dbi, xb.im[mu]));
   }
 }
 
@@ -38,8 +38,8 @@ template <typename T>
 __device__ __forceinline__ void caxpy_adj_y(T cr, T ci, const cv4<T>& accb, cv4<T>& yb) {
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    yb.re[mu] += cr * accb.re[mu] + ci * accb.im[mu];
-    yb.im[mu] += cr * accb.im[mu] - ci * accb.re[mu];
+    yb.re[mu] = fmac(ci, accb.im[mu], fmac(cr, accb.re[mu], yb.re[mu]));
+    yb.im[mu] = fmac(-ci, accb.re[mu], fmac(cr, accb.im[mu], yb.im[mu]));
   }
 }
 
@@ -48,8 +48,8 @@ template <typename T>
 __device__ __forceinline__ void caxpy_adj_c(const cv4<T>& y, const cv4<T>& accb, T& cbr, T& cbi) {
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    cbr += y.re[mu] * accb.re[mu] + y.im[mu] * accb.im[mu];
-    cbi += y.re[mu] * accb.im[mu] - y.im[mu] * accb.re[mu];
+    cbr = fmac(y.im[mu], accb.im[mu], fmac(y.re[mu], accb.re[mu], cbr));
+    cbi = fmac(-y.im[mu], accb.re[mu], fmac(y.re[mu], accb.im[mu], cbi));
   }
 }
 
@@ -312,7 +312,7 @@ __device__ __forceinline__ void rambo_q_adj(double r1, double r2, double r3, dou
   const double st = sqrt(1.0 - c * c);
   double sp, cp;
   sincospi(2.0 * r2, &sp, &cp);
-  const double q0 = -log(r3 * r4);
+  const double q0 = -log_fp64(r3 * r4);
   const double q0b = qb[0] + qb[1] * st * cp + qb[2] * st * sp + qb[3] * c;
   const double stb = q0 * (qb[1] * cp + qb[2] * sp);
   const double cpb = q0 * st * qb[1], spb = q0 * st * qb[2];

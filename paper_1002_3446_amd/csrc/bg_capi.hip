@@ -61,7 +61,35 @@ Shape shape_of(int n, int prec) {
   return s;
 }
 
-std::atomic<int> g_mixed_persistent{1};
+// strategy for several classes in one call (bg_set_mixed_launch)
+enum MixedMode { kSequential = 0, kPersistent = 1, kConcurrent = 2 };
+std::atomic<int> g_mixed_mode{kPersistent};
+
+// Side streams for concurrent classes: created once per device (default priority,
+// non-blocking), kept until the process ends.
+constexpr int kSideStreams = 4;
+int side_streams(hipStream_t** out) {
+  static std::mutex mu;
+  static hipStream_t pool[64][kSideStreams];
+  static bool ready[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BG_EHIP;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ready[dev]) {
+    for (int i = 0; i < kSideStreams; ++i)
+      if (hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking) != hipSuccess) return BG_EHIP;
+    ready[dev] = true;
+  }
+  *out = pool[dev];
+  return BG_OK;
+}
+
+// rough relative cost of one event (FP32; FP64 about three times), for balancing classes
+// over the side streams
+double event_cost(int n, int prec) {
+  static const double ns[13] = {0, 0, 0, 0, 0.31, 0.38, 0.47, 0.60, 0.75, 1.4, 2.7, 5.0, 8.7};
+  return ns[n] * (prec == 64 ? 3.0 : 1.0);
+}
 
 // compute units of the current device (cached per device)
 int cu_count() {
@@ -177,6 +205,15 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
 
 int from_hip(hipError_t e) { return e == hipSuccess ? BG_OK : BG_EHIP; }
 
+// Stream-ordered device workspace, released on the stream when the owner goes out of scope.
+struct Workspace {
+  double* p = nullptr;
+  hipStream_t s;
+  ~Workspace() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
 // Persistent multi-class launch over the classes ks (all of recursion precision prec):
 // tile list ordered by decreasing n, class table and tiles copied to a stream-ordered
 // workspace together with the zeroed tile counter.
@@ -249,13 +286,13 @@ const char* bg_strerror(int status) {
   }
 }
 
-int bg_set_mixed_launch(int persistent) {
-  if (persistent != 0 && persistent != 1) return BG_EINVAL;
-  g_mixed_persistent.store(persistent);
+int bg_set_mixed_launch(int mode) {
+  if (mode != kSequential && mode != kPersistent && mode != kConcurrent) return BG_EINVAL;
+  g_mixed_mode.store(mode);
   return BG_OK;
 }
 
-int bg_get_mixed_launch(void) { return g_mixed_persistent.load(); }
+int bg_get_mixed_launch(void) { return g_mixed_mode.load(); }
 
 int bg_set_launch(int n, int prec, int block, int tile_iters) {
   if (!table(n, prec)) return BG_ENOTSUP;
@@ -288,10 +325,32 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
     if (st != BG_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
-  // several FP32 classes: one persistent launch; FP64 classes (and a lone FP32 class) run
-  // their single-class kernels one after another below
+  // inverse-CDF tables of the classes that sample x1, x2: one stream-ordered workspace,
+  // released (stream-ordered) on every return path
+  Workspace tabs{nullptr, s};
+  {
+    int ntab = 0;
+    for (int k = 0; k < ncfg; ++k) ntab += (G[k].use_pdf && !G[k].in_x && G[k].count > 0) ? 1 : 0;
+    if (ntab > 0) {
+      if (hipMallocAsync((void**)&tabs.p, (size_t)ntab * kPdfSegs * 4 * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        tabs.p = nullptr;
+        return BG_ENOMEM;
+      }
+      int j = 0;
+      for (int k = 0; k < ncfg; ++k) {
+        if (!(G[k].use_pdf && !G[k].in_x && G[k].count > 0)) continue;
+        G[k].pdf.tab = tabs.p + (size_t)j++ * kPdfSegs * 4;
+        const int st = from_hip(launch_pdf_table(G[k].pdf, const_cast<double*>(G[k].pdf.tab), s));
+        if (st != BG_OK) return st;
+      }
+    }
+  }
+  const int mode = ncfg > 1 ? g_mixed_mode.load() : kSequential;
+  // persistent mode: the FP32 classes in one launch; FP64 classes run their single-class
+  // kernels below
   bool multi32 = false;
-  if (ncfg > 1 && g_mixed_persistent.load()) {
+  if (mode == kPersistent) {
     std::vector<int> ks;
     for (int k = 0; k < ncfg; ++k)
       if (cfgs[k].prec == 32 && G[k].count > 0) ks.push_back(k);
@@ -301,26 +360,78 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
       multi32 = true;
     }
   }
-  for (int k = 0; k < ncfg; ++k) {
-    if (G[k].count == 0 || (multi32 && cfgs[k].prec == 32)) continue;
-    const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
-    if (!L->generate) return BG_ENOTSUP;
-    const Shape sh = shape_of(cfgs[k].n, cfgs[k].prec);
-    const int block = lds_span_table(cfgs[k].n, cfgs[k].prec) ? kLdsLanes : sh.block;
-    const int64_t nblocks = (G[k].count + block - 1) / block;
-    double* partials = nullptr;
-    if (outs[k].acc) {
-      if (hipMallocAsync((void**)&partials, (size_t)nblocks * 4 * sizeof(double), s) != hipSuccess) {
-        (void)hipGetLastError();
-        return BG_ENOMEM;
-      }
-    }
-    int st = from_hip(L->generate(G[k], partials, block, s));
-    if (st == BG_OK && partials) st = from_hip(launch_finalize(partials, nblocks, outs[k].acc, s));
-    if (partials) (void)hipFreeAsync(partials, s);
-    if (st != BG_OK) return st;
+  std::vector<int> todo;
+  for (int k = 0; k < ncfg; ++k)
+    if (G[k].count > 0 && !(multi32 && cfgs[k].prec == 32)) todo.push_back(k);
+  if (todo.empty()) return BG_OK;
+  // per-class launch shapes and compensated-sum partials (allocated on the caller's stream
+  // before any fork, released on it after the join)
+  int block[16];
+  int64_t nblocks[16];
+  size_t off[16];
+  size_t bytes = 0;
+  for (int k : todo) {
+    if (!table(cfgs[k].n, cfgs[k].prec)->generate) return BG_ENOTSUP;
+    block[k] = lds_span_table(cfgs[k].n, cfgs[k].prec) ? kLdsLanes : shape_of(cfgs[k].n, cfgs[k].prec).block;
+    nblocks[k] = (G[k].count + block[k] - 1) / block[k];
+    off[k] = bytes;
+    if (outs[k].acc) bytes += (size_t)nblocks[k] * 4 * sizeof(double);
   }
-  return BG_OK;
+  Workspace parts{nullptr, s};
+  if (bytes > 0 && hipMallocAsync((void**)&parts.p, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    parts.p = nullptr;
+    return BG_ENOMEM;
+  }
+  auto run_class = [&](int k, hipStream_t t) {
+    double* partials = outs[k].acc ? parts.p + off[k] / sizeof(double) : nullptr;
+    int st = from_hip(table(cfgs[k].n, cfgs[k].prec)->generate(G[k], partials, block[k], t));
+    if (st == BG_OK && partials) st = from_hip(launch_finalize(partials, nblocks[k], outs[k].acc, t));
+    return st;
+  };
+  if (mode != kConcurrent || todo.size() < 2) {
+    for (int k : todo) {
+      const int st = run_class(k, s);
+      if (st != BG_OK) return st;
+    }
+    return BG_OK;
+  }
+  // concurrent mode: classes spread over the side streams (largest estimated work first,
+  // each to the least loaded stream), forked from and joined back into the caller's stream
+  hipStream_t* side = nullptr;
+  int st = side_streams(&side);
+  if (st != BG_OK) return st;
+  std::stable_sort(todo.begin(), todo.end(), [&](int a, int b) {
+    return G[a].count * event_cost(cfgs[a].n, cfgs[a].prec) > G[b].count * event_cost(cfgs[b].n, cfgs[b].prec);
+  });
+  hipEvent_t fork, join[kSideStreams];
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return BG_EHIP;
+  int nev = 0;
+  for (; nev < kSideStreams; ++nev)
+    if (hipEventCreateWithFlags(&join[nev], hipEventDisableTiming) != hipSuccess) break;
+  double load[kSideStreams] = {0.0};
+  bool used[kSideStreams] = {false};
+  st = nev == kSideStreams ? from_hip(hipEventRecord(fork, s)) : BG_EHIP;
+  for (size_t c = 0; c < todo.size() && st == BG_OK; ++c) {
+    const int k = todo[c];
+    const int t = (int)(std::min_element(load, load + kSideStreams) - load);
+    if (!used[t]) {
+      st = from_hip(hipStreamWaitEvent(side[t], fork, 0));
+      used[t] = true;
+    }
+    load[t] += G[k].count * event_cost(cfgs[k].n, cfgs[k].prec);
+    if (st == BG_OK) st = run_class(k, side[t]);
+  }
+  // join every stream that received work, also after a failed launch
+  for (int t = 0; t < kSideStreams && t < nev; ++t) {
+    if (!used[t]) continue;
+    const int j = from_hip(hipEventRecord(join[t], side[t]));
+    const int w = j == BG_OK ? from_hip(hipStreamWaitEvent(s, join[t], 0)) : j;
+    if (st == BG_OK) st = w;
+  }
+  (void)hipEventDestroy(fork);
+  for (int t = 0; t < nev; ++t) (void)hipEventDestroy(join[t]);
+  return st;
 }
 
 int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, const uint8_t* order,

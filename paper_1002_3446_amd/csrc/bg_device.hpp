@@ -14,6 +14,8 @@
 
 #include <type_traits>
 
+#include "bg_math.hpp"
+
 namespace bgk {
 
 // Compile-time loop: f(integral_constant<int, I>) for I = B .. E-1.  Every index of the
@@ -103,18 +105,32 @@ __device__ __forceinline__ uint64_t shuffle_order(const EventRng& rng) {
 
 // ----------------------------------------------------------------------------------------
 // Synthetic density f(x) = x^a (1-x)^b, b integer, with primitive F(x) = x^(a+1) P(x),
-// P(x) = sum_k C(b,k) (-1)^k x^k / (a+k+1), on [tau, 1); Z = F(1) - F(tau).
-// Inverse CDF by Newton's method in variables where the equation is nearly linear:
-//   x < x_split (u < u_split):  log(F(x) - F(tau)) = log(u Z)        in y = log x,
-//                               then one plain Newton step in x (tiny u: x close to tau);
-//   x >= x_split:               log(F(1) - F(x))   = log((1 - u) Z)  in z = log(1 - x),
-// where 1 - u is exact for u = (r + 1/2) 2^-32.  Converges in 3..7 steps.
+// P(x) = sum_k C(b,k) (-1)^k x^k / (a+k+1), on [tau, 1); Z = F(1) - F(tau).  x = F^-1(u):
+//
+// Per event: a cubic from a per-class table gives x to ~1e-4 relative; then Newton steps
+// on F(x) - F(tau) = u Z (u <= 1/2) or F(1) - F(x) = (1 - u) Z (u > 1/2), at least two and
+// until the step is below 1e-7 relative (from the table's accuracy: two).  One log and
+// one exp give w = x^(a+1) at the table point; each step moves x by x d and w by the
+// binomial series of (1 + d)^(a+1) to fourth order, exact in FP64 for |d| < 1e-3
+// (a larger step recomputes w).
+//
+// The table: u in [0, 1/2] in kPdfLowSeg equal segments; u > 1/2 by the binade of
+// s = 1 - u in [2^-33, 1/2) (kPdfBinades of them, each in kPdfSub equal parts of its
+// mantissa), which resolves the (1 - u)^(1/(b+1)) behaviour of x near 1.  Each segment
+// holds the cubic Hermite interpolant of x in the local coordinate theta in [0, 1), from
+// x and dx/dtheta = (Z / f(x)) du/dtheta at its ends; the ends are solved by pdf_solve.
 // ----------------------------------------------------------------------------------------
+constexpr int kPdfLowSeg = 64;
+constexpr int kPdfBinades = 32;  // s in [2^-33, 2^-1)
+constexpr int kPdfSub = 8;
+constexpr int kPdfSegs = kPdfLowSeg + kPdfBinades * kPdfSub;
+
 struct PdfParams {
   double a, tau, Ftau, F1, Z, x0base;  // x0base = tau^(a+1)
   double usplit, xsplit;
   double coef[17];
   int b;
+  const double* tab;  // [kPdfSegs][4] cubic coefficients, filled by k_pdf_table
 };
 
 __device__ __forceinline__ double ipow(double x, int k) {
@@ -123,69 +139,134 @@ __device__ __forceinline__ double ipow(double x, int k) {
   return r;
 }
 
-// Both parton fractions in one loop (two independent Newton chains, interleaved).  Per x:
-// v = log x (lower branch) or v = log(1 - x) (upper branch); each step costs exp(v),
-// exp((a+1) log x), log G and one division; log x = v on the lower branch.
-__device__ inline void pdf_sample2(double u1, double u2, const PdfParams& P, double& x1, double& x2) {
+__device__ __forceinline__ double pdf_poly(const PdfParams& P, double x) {
+  double poly = P.coef[P.b];
+  for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, x, P.coef[k]);
+  return poly;
+}
+
+// Robust solve of one table node (setup only).  Newton's method in variables where the
+// equation is nearly linear:
+//   x < x_split (u < u_split):  log(F(x) - F(tau)) = log(u Z)        in y = log x,
+//                               then one plain Newton step in x (x close to tau);
+//   x >= x_split:               log(F(1) - F(x))   = log((1 - u) Z)  in z = log(1 - x);
+// s = 1 - u is passed exactly.  Converges in 3..7 steps; at most 40.
+__device__ inline double pdf_solve(double u, double s, const PdfParams& P) {
+  if (u <= 0.0) return P.tau;
   const double ap1 = P.a + 1.0;
-  const double uu[2] = {u1, u2};
-  bool lower[2], done[2];
-  double v[2], target[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    lower[j] = uu[j] < P.usplit;
-    done[j] = false;
-    if (lower[j]) {
-      const double T = uu[j] * P.Z;
-      target[j] = log(T);
-      const double base = P.x0base + ap1 * T;  // leading power only
-      double lx = base > 0.0 ? log(base) / ap1 : log(P.xsplit);
-      v[j] = fmin(fmax(lx, log(P.tau) + 1e-12), log(P.xsplit));
+  const bool lower = u < P.usplit;
+  double v, target;
+  if (lower) {
+    const double T = u * P.Z;
+    target = log(T);
+    const double base = P.x0base + ap1 * T;  // leading power only
+    const double lx = base > 0.0 ? log(base) / ap1 : log(P.xsplit);
+    v = fmin(fmax(lx, log(P.tau) + 1e-12), log(P.xsplit));
+  } else {
+    target = log(s * P.Z);
+    v = -0.69314718055994530942;  // x = 1/2
+  }
+  for (int it = 0; it < 40; ++it) {
+    const double e = exp(v);
+    const double x = lower ? e : 1.0 - e;
+    const double lx = lower ? v : log1p(-e);
+    const double xa1 = exp(ap1 * lx);
+    const double F = xa1 * pdf_poly(P, x);
+    const double G = lower ? F - P.Ftau : P.F1 - F;
+    const double omx_b = ipow(1.0 - x, P.b);
+    // d log G / dv = x f / G (lower) or (1 - x) f / G (upper), with f = x^a (1-x)^b
+    const double dG = lower ? xa1 * omx_b : xa1 / x * omx_b * (1.0 - x);
+    if (!(G > 0.0)) {  // stepped outside the domain: restart inside it
+      v = lower ? log(P.tau) + 1e-9 : -0.69314718055994530942;
+      continue;
+    }
+    const double step = (log(G) - target) * G / dG;
+    v -= step;
+    if (fabs(step) <= 1e-9) break;
+  }
+  double x = lower ? exp(v) : 1.0 - exp(v);
+  if (lower) {  // one plain Newton step in x: exact where x is close to tau
+    const double xa1 = exp(ap1 * v);
+    const double f = xa1 / x * ipow(1.0 - x, P.b);
+    x -= (xa1 * pdf_poly(P, x) - P.Ftau - u * P.Z) / f;
+  }
+  return x;
+}
+
+// Segment and local coordinate of u (see above).  u <= 1/2 uses u itself; u > 1/2 the exact
+// s = 1 - u, split by frexp into binade and mantissa.
+__device__ __forceinline__ int pdf_segment(double u, double& theta) {
+  if (u <= 0.5) {
+    const double t = u * (2 * kPdfLowSeg);
+    const int k = min(max((int)t, 0), kPdfLowSeg - 1);
+    theta = t - k;
+    return k;
+  }
+  int e;
+  const double m = frexp(1.0 - u, &e);  // 1 - u = m 2^e, m in [1/2, 1)
+  const int bin = min(max(e + 32, 0), kPdfBinades - 1);  // e = -32 .. -1 for s in [2^-33, 1/2)
+  const double t = (ldexp(1.0 - u, 33 - bin) - 1.0) * kPdfSub;  // s / 2^(bin-33) in [1, 2)
+  const int j = min(max((int)t, 0), kPdfSub - 1);
+  theta = t - j;
+  return kPdfLowSeg + bin * kPdfSub + j;
+}
+
+// u of a segment's local coordinate (the inverse of pdf_segment), with s = 1 - u exact
+__device__ __forceinline__ void pdf_node(int seg, double theta, double& u, double& s, double& dudtheta) {
+  if (seg < kPdfLowSeg) {
+    u = (seg + theta) / (2 * kPdfLowSeg);
+    s = 1.0 - u;
+    dudtheta = 1.0 / (2 * kPdfLowSeg);
+    return;
+  }
+  const int bin = (seg - kPdfLowSeg) / kPdfSub, j = (seg - kPdfLowSeg) % kPdfSub;
+  const double scale = ldexp(1.0, bin - 33);  // binade [2^(bin-33), 2^(bin-32))
+  s = (1.0 + (j + theta) / kPdfSub) * scale;
+  u = 1.0 - s;
+  dudtheta = -scale / kPdfSub;
+}
+
+// x = F^-1(u) for one parton (see above).
+__device__ __forceinline__ double pdf_sample(double u, const PdfParams& P) {
+  const double A = P.a + 1.0;
+  double theta;
+  const int seg = pdf_segment(u, theta);
+  const double* c = P.tab + 4 * seg;
+  double x = fma(fma(fma(c[3], theta, c[2]), theta, c[1]), theta, c[0]);
+  x = fmin(fmax(x, P.tau), 1.0 - 0x1p-53);
+  double w = exp(A * log_fp64(x));
+  const bool lower = u <= 0.5;
+  const double uZ = lower ? u * P.Z : (1.0 - u) * P.Z;
+  const double c1 = A, c2 = A * (A - 1.0) / 2.0, c3 = c2 * (A - 2.0) / 3.0, c4 = c3 * (A - 3.0) / 4.0;
+  double d = 1.0;
+  for (int it = 0; it < 8 && (it < 2 || fabs(d) > 1e-7); ++it) {
+    const double F = w * pdf_poly(P, x);
+    const double res = lower ? (F - P.Ftau) - uZ : uZ - (P.F1 - F);
+    // Newton: dx = -res / f(x), f = (w / x) (1 - x)^b, so d = dx / x = -res / (w (1 - x)^b)
+    d = -res / (w * ipow(1.0 - x, P.b));
+    x = fma(x, d, x);
+    if (fabs(d) < 1e-3) {
+      w *= 1.0 + d * (c1 + d * (c2 + d * (c3 + d * c4)));
     } else {
-      target[j] = log((1.0 - uu[j]) * P.Z);
-      v[j] = -0.69314718055994530942;  // x = 1/2
+      x = fmin(fmax(x, P.tau), 1.0 - 0x1p-53);
+      w = exp(A * log_fp64(x));
     }
   }
-  for (int it = 0; it < 16; ++it) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (done[j]) continue;
-      const double e = exp(v[j]);
-      const double x = lower[j] ? e : 1.0 - e;
-      const double lx = lower[j] ? v[j] : log1p(-e);
-      const double xa1 = exp(ap1 * lx);
-      double poly = P.coef[P.b];
-      for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, x, P.coef[k]);
-      const double F = xa1 * poly;
-      const double G = lower[j] ? F - P.Ftau : P.F1 - F;
-      const double omx_b = ipow(1.0 - x, P.b);
-      // d log G / dv = x f / G (lower) or (1 - x) f / G (upper), with f = x^a (1-x)^b
-      const double dG = lower[j] ? xa1 * omx_b : xa1 / x * omx_b * (1.0 - x);
-      if (!(G > 0.0)) {  // stepped outside the domain: restart inside it
-        v[j] = lower[j] ? log(P.tau) + 1e-9 : -0.69314718055994530942;
-        continue;
-      }
-      const double step = (log(G) - target[j]) * G / dG;
-      v[j] -= step;
-      done[j] = fabs(step) <= 1e-9;
-    }
-    if (done[0] && done[1]) break;
-  }
-  double xs[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const double e = exp(v[j]);
-    xs[j] = lower[j] ? e : 1.0 - e;
-    if (lower[j]) {  // one plain Newton step in x: exact where x is close to tau
-      const double xa1 = exp(ap1 * v[j]);
-      double poly = P.coef[P.b];
-      for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, xs[j], P.coef[k]);
-      const double f = xa1 / xs[j] * ipow(1.0 - xs[j], P.b);
-      xs[j] -= (xa1 * poly - P.Ftau - uu[j] * P.Z) / f;
-    }
-  }
-  x1 = xs[0];
-  x2 = xs[1];
+  return x;
+}
+
+// Table setup: one thread per segment.
+__device__ __forceinline__ void pdf_table_segment(const PdfParams& P, int seg, double* out) {
+  double u0, s0, du0, u1, s1, du1;
+  pdf_node(seg, 0.0, u0, s0, du0);
+  pdf_node(seg, 1.0, u1, s1, du1);
+  const double x0 = pdf_solve(u0, s0, P), x1 = pdf_solve(u1, s1, P);
+  const double f0 = exp(P.a * log(x0)) * ipow(1.0 - x0, P.b), f1 = exp(P.a * log(x1)) * ipow(1.0 - x1, P.b);
+  const double d0 = P.Z / f0 * du0, d1 = P.Z / f1 * du1;  // dx/dtheta at the ends
+  out[0] = x0;
+  out[1] = d0;
+  out[2] = 3.0 * (x1 - x0) - 2.0 * d0 - d1;
+  out[3] = 2.0 * (x0 - x1) + d0 + d1;
 }
 
 // ----------------------------------------------------------------------------------------
@@ -197,7 +278,7 @@ __device__ __forceinline__ void rambo_q(double r1, double r2, double r3, double 
   const double st = sqrt(1.0 - c * c);
   double sp, cp;
   sincospi(2.0 * r2, &sp, &cp);
-  const double q0 = -log(r3 * r4);
+  const double q0 = -log_fp64(r3 * r4);
   q[0] = q0;
   q[1] = q0 * st * cp;
   q[2] = q0 * st * sp;
@@ -234,19 +315,33 @@ struct cv4 {
 
 // eps_h(p) = (0, -h ct cf + i sf, -h ct sf - i cf, h st) / sqrt(2) from the physical momentum,
 // evaluated in the recursion precision T (the vector only enters the recursion in T).
+// In FP32 the two inverse lengths come from the hardware reciprocal square root (about
+// one ulp), in FP64 from correctly rounded square roots and divisions.
 template <typename T>
 __device__ __forceinline__ cv4<T> polarisation(const double p[4], bool plus) {
   const T px = T(p[1]), py = T(p[2]), pz = T(p[3]);
   const T pt2 = px * px + py * py;
-  const T pa = sqrt(pt2 + pz * pz);
-  const T pt = sqrt(pt2);
-  const T ipa = T(1) / pa;
-  const T ct = pz * ipa, st = pt * ipa;
-  T cf = T(1), sf = T(0);
-  if (pt2 > T(0)) {
-    const T ipt = T(1) / pt;
-    cf = px * ipt;
-    sf = py * ipt;
+  T ct, st, cf = T(1), sf = T(0);
+  if constexpr (std::is_same<T, float>::value) {
+    const float ipa = __builtin_amdgcn_rsqf(pt2 + pz * pz);
+    const float ipt = __builtin_amdgcn_rsqf(pt2);
+    ct = pz * ipa;
+    st = pt2 > 0.0f ? (pt2 * ipt) * ipa : 0.0f;
+    if (pt2 > 0.0f) {
+      cf = px * ipt;
+      sf = py * ipt;
+    }
+  } else {
+    const T pa = sqrt(pt2 + pz * pz);
+    const T pt = sqrt(pt2);
+    const T ipa = T(1) / pa;
+    ct = pz * ipa;
+    st = pt * ipa;
+    if (pt2 > T(0)) {
+      const T ipt = T(1) / pt;
+      cf = px * ipt;
+      sf = py * ipt;
+    }
   }
   const T r = T(0.70710678118654752440);
   const T h = plus ? r : -r;
@@ -340,7 +435,8 @@ struct SpanKLds {
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) acc[mu] += k[b][mu];
         kt[SP::at(a, b) * LANES] = make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
-        if (b - a + 1 < L) pt[SP::at(a, b) * LANES] = float(1.0 / minkowski_sq(acc));
+        // K^2 in FP64, its reciprocal in FP32 (within 1 ulp of the rounded K^2's)
+        if (b - a + 1 < L) pt[SP::at(a, b) * LANES] = __builtin_amdgcn_rcpf(float(minkowski_sq(acc)));
       });
     });
   }
@@ -358,25 +454,35 @@ struct SpanKLds {
   }
 };
 
+// Fused multiply-add a * b + c with one rounding, in the precision of the operands.  The
+// complex products below are written as chains of these (one accumulator per real part),
+// which halves the separate adds a contracted a*b - c*d form would leave.
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// r + i i = x . y, bilinear with the metric (+,-,-,-)
 template <typename T>
 __device__ __forceinline__ void cdot(const cv4<T>& x, const cv4<T>& y, T& r, T& i) {
-  r = x.re[0] * y.re[0] - x.im[0] * y.im[0];
-  i = x.re[0] * y.im[0] + x.im[0] * y.re[0];
+  r = fmac(-x.im[0], y.im[0], x.re[0] * y.re[0]);
+  i = fmac(x.im[0], y.re[0], x.re[0] * y.im[0]);
 #pragma unroll
   for (int mu = 1; mu < 4; ++mu) {
-    r -= x.re[mu] * y.re[mu] - x.im[mu] * y.im[mu];
-    i -= x.re[mu] * y.im[mu] + x.im[mu] * y.re[mu];
+    r = fmac(-x.re[mu], y.re[mu], r);
+    r = fmac(x.im[mu], y.im[mu], r);
+    i = fmac(-x.re[mu], y.im[mu], i);
+    i = fmac(-x.im[mu], y.re[mu], i);
   }
 }
 
+// r + i i = x . k for a real four-vector k
 template <typename T>
 __device__ __forceinline__ void rdot(const cv4<T>& x, const T k[4], T& r, T& i) {
   r = x.re[0] * k[0];
   i = x.im[0] * k[0];
 #pragma unroll
   for (int mu = 1; mu < 4; ++mu) {
-    r -= x.re[mu] * k[mu];
-    i -= x.im[mu] * k[mu];
+    r = fmac(-x.re[mu], k[mu], r);
+    i = fmac(-x.im[mu], k[mu], i);
   }
 }
 
@@ -385,8 +491,8 @@ template <typename T>
 __device__ __forceinline__ void caxpy(T cr, T ci, const cv4<T>& y, cv4<T>& acc) {
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    acc.re[mu] += cr * y.re[mu] - ci * y.im[mu];
-    acc.im[mu] += cr * y.im[mu] + ci * y.re[mu];
+    acc.re[mu] = fmac(-ci, y.im[mu], fmac(cr, y.re[mu], acc.re[mu]));
+    acc.im[mu] = fmac(ci, y.re[mu], fmac(cr, y.im[mu], acc.im[mu]));
   }
 }
 

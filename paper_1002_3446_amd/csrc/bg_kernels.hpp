@@ -58,7 +58,8 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
       ev.x1 = C.in_x[2 * i];
       ev.x2 = C.in_x[2 * i + 1];
     } else {
-      pdf_sample2(u01(b0.v[0]), u01(b0.v[1]), C.pdf, ev.x1, ev.x2);
+      ev.x1 = pdf_sample(u01(b0.v[0]), C.pdf);
+      ev.x2 = pdf_sample(u01(b0.v[1]), C.pdf);
     }
     ev.shat = ev.x1 * ev.x2 * C.sqrt_s * C.sqrt_s;
     sqrt_shat = sqrt(ev.shat);
@@ -136,6 +137,21 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
   }
 }
 
+// eta = asinh(pz / pT) of a momentum with transverse momentum pT, as sign(pz) log1p(x) with
+// x = r (1 + |pz| / (|p| + pT)), r = |pz| / pT: the same function, since
+// |p| - pT = pz^2 / (|p| + pT).  log1p(x) is taken as log(u) x / (u - 1) with u = 1 + x
+// (Goldberg's construction, a few ulp), so small |eta| keeps its relative precision;
+// pT = 0 gives +-inf.
+__device__ __forceinline__ double pseudorapidity(double pt, double pz) {
+  const double az = fabs(pz);
+  const double pabs = sqrt(pt * pt + az * az);
+  const double x = (az / pt) * (1.0 + az / (pabs + pt));
+  const double u = 1.0 + x;
+  const double d = u - 1.0;
+  const double e = d == 0.0 ? x : (isinf(x) ? x : log_fp64(u) * (x / d));
+  return copysign(e, pz);
+}
+
 // Jet cuts and observables (Sec. 3, Sec. 4) on the outgoing legs.
 template <int N>
 __device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, double& ht, double& rmin) {
@@ -146,7 +162,7 @@ __device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, d
   for (int t = 1; t < N; ++t) {
     const double* p = ev.p[t];
     pt[t] = sqrt(p[1] * p[1] + p[2] * p[2]);
-    eta[t] = asinh(p[3] / pt[t]);
+    eta[t] = pseudorapidity(pt[t], p[3]);
     phi[t] = atan2(p[2], p[1]);
     const bool out = ev.leg[t] >= 2u;
     if (out) {

@@ -45,6 +45,9 @@ struct Launchers {
 
 hipError_t launch_finalize(const double* partials, int64_t nparts, double* acc, hipStream_t s);
 
+// Fills tab[kPdfSegs][4] (device) with the inverse-CDF table of P's density.
+hipError_t launch_pdf_table(const PdfParams& P, double* tab, hipStream_t s);
+
 // One class of a multi-class launch and one tile of its work list (device-resident).
 struct MultiClass {
   GenClass C;

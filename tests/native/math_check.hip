@@ -1,0 +1,31 @@
+// Host-side driver for the accuracy test of the library's FP64 elementary functions:
+// prints x and f(x) in hexadecimal for arguments spread over many binades.
+#include <cstdint>
+#include <cstdio>
+
+#include "../../paper_1002_3446_amd/csrc/bg_math.hpp"
+
+int main() {
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    st ^= st << 13;
+    st ^= st >> 7;
+    st ^= st << 17;
+    return st;
+  };
+  for (int i = 0; i < 200000; ++i) {
+    const uint64_t r = next();
+    // uniform mantissa, exponent uniform in [-80, 40], plus values near 1
+    double x;
+    if (i % 4 == 0) {
+      x = 1.0 + ((double)(int64_t)(r >> 11) - 0x1p52) * 0x1p-62;
+    } else {
+      const double m = 1.0 + (double)(r >> 12) * 0x1p-52;
+      x = std::ldexp(m, (int)(r % 121) - 80);
+    }
+    std::printf("%a %a\n", x, bgk::log_fp64(x));
+  }
+  const double edge[] = {0x1p-1074, 0x1p-1022, 0x1.fffffffffffffp1023, 1.0, 0.5, 2.0, 0.7071067811865476, 1.4142135623730951};
+  for (double x : edge) std::printf("%a %a\n", x, bgk::log_fp64(x));
+  return 0;
+}

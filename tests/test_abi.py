@@ -62,7 +62,8 @@ def test_host_error_paths():
     assert lib.bg_set_launch(8, 32, 96, 1) == bg.BG_EINVAL
     assert lib.bg_set_launch(8, 32, 128, 0) == bg.BG_EINVAL
     assert lib.bg_set_launch(2, 32, 128, 1) == bg.BG_ENOTSUP
-    assert lib.bg_set_mixed_launch(2) == bg.BG_EINVAL
+    assert lib.bg_set_mixed_launch(3) == bg.BG_EINVAL and lib.bg_set_mixed_launch(-1) == bg.BG_EINVAL
+    assert lib.bg_set_mixed_launch(2) == bg.BG_OK and lib.bg_get_mixed_launch() == 2
     assert lib.bg_set_mixed_launch(0) == bg.BG_OK and lib.bg_get_mixed_launch() == 0
     assert lib.bg_set_mixed_launch(1) == bg.BG_OK and lib.bg_get_mixed_launch() == 1
     b, k = ctypes.c_int(), ctypes.c_int()
