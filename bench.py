@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--events", type=int, default=1 << 24)
     ap.add_argument("--no-extras", action="store_true", help="main line only (used under profilers)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--recursion", action="store_true",
+                    help="with --no-extras: still time the recursion kernel (bg_amp2) alone")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM counters)")
     a = ap.parse_args()
@@ -285,6 +287,8 @@ def main():
     acc = out["acc"].cpu().numpy()
     line["sigma_pb_last_step"] = float((acc[0] + acc[1]) / N)
 
+    if a.recursion and a.no_extras:
+        line["recursion_kernel"] = recursion_rate(bg, torch)
     if not a.no_extras:
         extras = {}
         cfg64 = bg.config(n, prec=64, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)

@@ -139,6 +139,16 @@ int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const 
 int bg_set_launch(int n, int prec, int block, int tile_iters);
 int bg_get_launch(int n, int prec, int *block, int *tile_iters);
 
+/* Lanes of a wave that share one event in the single-class kernels of (n, prec) (bg_generate
+ * and bg_amp2; the persistent multi-class kernel and bg_amp2_grad use one lane per event):
+ * 1, or 2 where the library holds the two-lane form (FP32 n >= 9, FP64 n >= 6; else
+ * BG_ENOTSUP); 0 restores the default (2 for FP32 n >= 10 and FP64 n >= 7, else 1).  With
+ * two lanes each holds two of the four Lorentz components of every current: half the
+ * registers, at the price of cross-lane sums in every Minkowski product.  Affects speed
+ * only: |A|^2 agrees to the recursion precision's rounding between the forms. */
+int bg_set_lanes(int n, int prec, int lanes);
+int bg_get_lanes(int n, int prec, int *lanes);
+
 /* Strategy for bg_generate calls with several classes (process-wide setting):
  *   0  each class's single-class kernel, one after another on the caller's stream;
  *   1  (default) the FP32 classes in one persistent launch (FP64 classes as in 0);

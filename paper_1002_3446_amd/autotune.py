@@ -1,14 +1,15 @@
 """Launch-shape autotuner for libbg (needs a GPU).
 
 For every multiplicity n and recursion precision it times single-class bg_generate with
-64, 128 and 256 threads per workgroup and keeps the fastest; then, on the mixed workload
+64, 128 and 256 threads per workgroup and, where the library holds both, one or two lanes
+per event, and keeps the fastest; then, on the FP32 mixed workload
 (n = 4..12 with 2^(26-n) events each, one persistent launch), it tunes each class's tile
 length (events per lane per tile) by coordinate search, and finally records which of the
 three strategies for several classes (one after another, one persistent launch, classes on
 concurrent streams) is fastest for that workload.  The result is written to
 autotune.json next to this file, which the binding applies on import.
 
-Usage: python -m paper_1002_3446_amd.autotune [--prec 32] [--out PATH] [--scale S]
+Usage: python -m paper_1002_3446_amd.autotune [--prec 32|64|both] [--out PATH] [--scale S]
 """
 from __future__ import annotations
 
@@ -45,21 +46,37 @@ def mixed_workload(prec, scale=0):
     return cfgs, counts
 
 
-def tune(prec=32, scale=0, log=print):
+def lane_forms(n, prec):
+    """Lanes-per-event forms the library holds for (n, prec)."""
+    return (1, 2) if (prec == 32 and n >= 9) or (prec == 64 and n >= 6) else (1,)
+
+
+def tune_single(prec=32, scale=0, log=print):
+    """Workgroup size and lanes per event of every single-class kernel."""
     shapes = {}
     for n in NS:
         N = 1 << max(20 - scale, 26 - n - scale)
         cfg = bg.config(n, prec=prec, seed=0xB6000003 + n)
         out = bg.generate(cfg, N, outputs=("weight", "acc"))
         best = None
-        for block in (64, 128, 256):
-            bg.set_launch(n, prec, block, bg.get_launch(n, prec)[1] or 1)
-            t = _time(lambda: bg.generate(cfg, N, outputs=("weight", "acc"), out_tensors=[out]))
-            log(f"n={n} prec={prec} block={block}: {t:.3f} ms for {N} events")
-            if best is None or t < best[0]:
-                best = (t, block)
-        shapes[n] = [best[1], bg.get_launch(n, prec)[1]]
+        for lanes in lane_forms(n, prec):
+            bg.set_lanes(n, prec, lanes)
+            for block in (64, 128, 256):
+                bg.set_launch(n, prec, block, bg.get_launch(n, prec)[1] or 1)
+                t = _time(lambda: bg.generate(cfg, N, outputs=("weight", "acc"), out_tensors=[out]))
+                log(f"n={n} prec={prec} lanes={lanes} block={block}: {t:.3f} ms for {N} events")
+                if best is None or t < best[0]:
+                    best = (t, block, lanes)
+        shapes[n] = [best[1], bg.get_launch(n, prec)[1], best[2]]
         bg.set_launch(n, prec, shapes[n][0], shapes[n][1])
+        bg.set_lanes(n, prec, shapes[n][2])
+    return shapes
+
+
+def tune(prec=32, scale=0, log=print):
+    shapes = tune_single(prec, scale, log)
+    if prec != 32:   # the persistent multi-class kernel is FP32 only
+        return [dict(n=n, prec=prec, block=b, tile_iters=i, lanes=l) for n, (b, i, l) in shapes.items()], None
     cfgs, counts = mixed_workload(prec, scale)
     outs = bg.generate(cfgs, counts, outputs=("weight", "acc"))
     run = lambda: bg.generate(cfgs, counts, outputs=("weight", "acc"), out_tensors=outs)
@@ -82,28 +99,33 @@ def tune(prec=32, scale=0, log=print):
         modes[name] = _time(run)
     bg.set_mixed_launch(bg.MIXED_PERSISTENT)
     log("mixed workload: " + ", ".join(f"{k} {v:.3f} ms" for k, v in modes.items()))
-    return [dict(n=n, prec=prec, block=b, tile_iters=i) for n, (b, i) in shapes.items()], modes
+    return [dict(n=n, prec=prec, block=b, tile_iters=i, lanes=l) for n, (b, i, l) in shapes.items()], modes
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--prec", type=int, default=32)
+    ap.add_argument("--prec", default="both", choices=("32", "64", "both"))
     ap.add_argument("--scale", type=int, default=0, help="shrink every workload by 2^scale")
     ap.add_argument("--out", default=bg.TUNING_PATH)
     a = ap.parse_args()
+    precs = (32, 64) if a.prec == "both" else (int(a.prec),)
     t0 = time.time()
-    for n in NS:
-        bg.set_launch(n, a.prec, 0, 0)   # start from the built-in defaults
+    for prec in precs:
+        for n in NS:
+            bg.set_launch(n, prec, 0, 0)   # start from the built-in defaults
+            bg.set_lanes(n, prec, 0)
     bg.set_mixed_launch(bg.MIXED_PERSISTENT)
-    shapes, modes = tune(a.prec, a.scale)
-    ids = {"sequential": bg.MIXED_SEQUENTIAL, "persistent": bg.MIXED_PERSISTENT, "concurrent": bg.MIXED_CONCURRENT}
-    best = min(modes, key=modes.get)
-    doc = {"device": torch.cuda.get_device_name(0), "mixed_ms": modes, "mixed_mode": ids[best],
-           "mixed_mode_name": best, "tuned_in_s": time.time() - t0, "shapes": shapes}
-    if os.path.exists(a.out):
-        old = json.load(open(a.out))
-        keep = [e for e in old.get("shapes", []) if e["prec"] != a.prec]
-        doc["shapes"] = keep + shapes
+    doc = json.load(open(a.out)) if os.path.exists(a.out) else {}
+    shapes = [e for e in doc.get("shapes", []) if e["prec"] not in precs]
+    for prec in precs:
+        sh, modes = tune(prec, a.scale)
+        shapes += sh
+        if modes is not None:
+            ids = {"sequential": bg.MIXED_SEQUENTIAL, "persistent": bg.MIXED_PERSISTENT,
+                   "concurrent": bg.MIXED_CONCURRENT}
+            best = min(modes, key=modes.get)
+            doc.update({"mixed_ms": modes, "mixed_mode": ids[best], "mixed_mode_name": best})
+    doc.update({"device": torch.cuda.get_device_name(0), "tuned_in_s": time.time() - t0, "shapes": shapes})
     with open(a.out, "w") as f:
         json.dump(doc, f, indent=1)
     print(json.dumps(doc))

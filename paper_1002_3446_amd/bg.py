@@ -51,12 +51,14 @@ _lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c
 _lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 9
 _lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
 _lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.bg_set_lanes.argtypes = [ctypes.c_int] * 3
+_lib.bg_get_lanes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.bg_set_mixed_launch.argtypes = [ctypes.c_int]
 _lib.bg_get_mixed_launch.argtypes = []
 _lib.bg_strerror.restype = ctypes.c_char_p
 _lib.bg_strerror.argtypes = [ctypes.c_int]
 for _f in ("bg_generate", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
-           "bg_set_mixed_launch", "bg_get_mixed_launch"):
+           "bg_set_mixed_launch", "bg_get_mixed_launch", "bg_set_lanes", "bg_get_lanes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -205,6 +207,17 @@ def get_launch(n: int, prec: int):
     return b.value, c.value
 
 
+def set_lanes(n: int, prec: int, lanes: int):
+    """Lanes per event of the single-class kernels of (n, prec): 1, 2 or 0 (default)."""
+    _check("bg_set_lanes", _lib.bg_set_lanes(n, prec, lanes))
+
+
+def get_lanes(n: int, prec: int) -> int:
+    v = ctypes.c_int()
+    _check("bg_get_lanes", _lib.bg_get_lanes(n, prec, ctypes.byref(v)))
+    return v.value
+
+
 MIXED_SEQUENTIAL, MIXED_PERSISTENT, MIXED_CONCURRENT = 0, 1, 2
 
 
@@ -231,6 +244,8 @@ def load_tuning(path: str = TUNING_PATH) -> int:
     entries = doc.get("shapes", [])
     for e in entries:
         set_launch(int(e["n"]), int(e["prec"]), int(e["block"]), int(e["tile_iters"]))
+        if "lanes" in e:
+            set_lanes(int(e["n"]), int(e["prec"]), int(e["lanes"]))
     if "mixed_mode" in doc:
         set_mixed_launch(int(doc["mixed_mode"]))
     return len(entries)

@@ -40,8 +40,7 @@ GRAD_MAX_N = 10    # the fully unrolled adjoint of n = 11, 12 would need 4-8x th
 
 def units_for(ns, precs=(32, 64), kinds=KINDS):
     units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"), [], 0),
-             (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0),
-             (os.path.join(CSRC, "bg_pdf.hip"), os.path.join(OUT_DIR, "bg_pdf.o"), [], 0)]
+             (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0)]
     # the persistent multi-class kernel holds every multiplicity: start it first
     units.append((os.path.join(CSRC, "bg_multi.hip"), os.path.join(OUT_DIR, "bg_multi_p32.o"), [], 1000))
     for n in ns:
@@ -57,20 +56,23 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
     return units
 
 
-def _newest_source() -> float:
-    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(PKG, "..", "include", "bg.h")]
-    return max(os.path.getmtime(f) for f in srcs)
+def _deps_mtime(src: str) -> float:
+    """Newest modification time of a unit's inputs: its own source, every header in csrc/
+    and include/bg.h (other .hip files are not inputs)."""
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    hdrs.append(os.path.join(PKG, "..", "include", "bg.h"))
+    return max(os.path.getmtime(f) for f in hdrs + [src])
 
 
 def build(jobs: int | None = None, verbose: bool = True, ns=range(4, 13), incremental: bool = False) -> str:
     """Compiles every unit for the multiplicities ns and links libbg.so.  incremental=True
-    keeps objects newer than every source (developer convenience; the default rebuilds all)."""
+    keeps objects newer than their unit's inputs (developer convenience; the default
+    rebuilds all)."""
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     units = units_for(list(ns))
     if incremental:
-        newest = _newest_source()
-        done = [u for u in units if os.path.exists(u[1]) and os.path.getmtime(u[1]) > newest]
+        done = [u for u in units if os.path.exists(u[1]) and os.path.getmtime(u[1]) > _deps_mtime(u[0])]
         units_todo = [u for u in units if u not in done]
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
             list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units_todo))
@@ -98,6 +100,6 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--ns", type=str, default="4,5,6,7,8,9,10,11,12",
                     help="comma-separated multiplicities to build (others report BG_ENOTSUP)")
-    ap.add_argument("--incremental", action="store_true", help="reuse objects newer than every source")
+    ap.add_argument("--incremental", action="store_true", help="reuse objects newer than their unit's inputs")
     a = ap.parse_args()
     build(a.jobs, ns=[int(x) for x in a.ns.split(",")], incremental=a.incremental)

@@ -19,7 +19,11 @@
                                                                     hipStream_t);                         \
   __attribute__((weak)) hipError_t launch_amp2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*,  \
                                                                 const uint8_t*, double*, int, hipStream_t); \
-  __attribute__((weak)) hipError_t launch_grad_n##N##_p##P##_k2(const GradArgs&, int, hipStream_t);
+  __attribute__((weak)) hipError_t launch_grad_n##N##_p##P##_k2(const GradArgs&, int, hipStream_t);       \
+  __attribute__((weak)) hipError_t launch_generate2_n##N##_p##P##_k0(const GenClass&, double*, int,       \
+                                                                     hipStream_t);                        \
+  __attribute__((weak)) hipError_t launch_amp2_2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*, \
+                                                                  const uint8_t*, double*, int, hipStream_t);
 #define BG_DECL(N) BG_DECL_ONE(N, 32) BG_DECL_ONE(N, 64)
 namespace bgk {
 BG_DECL(4) BG_DECL(5) BG_DECL(6) BG_DECL(7) BG_DECL(8) BG_DECL(9) BG_DECL(10) BG_DECL(11) BG_DECL(12)
@@ -30,8 +34,10 @@ namespace {
 using namespace bgk;
 
 #define BG_ROW(N)                                                                                       \
-  {{launch_generate_n##N##_p32_k0, launch_amp2_n##N##_p32_k1, launch_grad_n##N##_p32_k2},               \
-   {launch_generate_n##N##_p64_k0, launch_amp2_n##N##_p64_k1, launch_grad_n##N##_p64_k2}}
+  {{launch_generate_n##N##_p32_k0, launch_amp2_n##N##_p32_k1, launch_grad_n##N##_p32_k2,                \
+    launch_generate2_n##N##_p32_k0, launch_amp2_2_n##N##_p32_k1},                                       \
+   {launch_generate_n##N##_p64_k0, launch_amp2_n##N##_p64_k1, launch_grad_n##N##_p64_k2,                \
+    launch_generate2_n##N##_p64_k0, launch_amp2_2_n##N##_p64_k1}}
 
 const Launchers* table(int n, int prec) {
   static const Launchers t[9][2] = {BG_ROW(4),  BG_ROW(5),  BG_ROW(6), BG_ROW(7), BG_ROW(8),
@@ -48,6 +54,13 @@ struct Shape {
 };
 std::mutex g_shape_mu;
 Shape g_shape[13][2];
+int g_lanes[13][2];  // lanes per event of single-class kernels (0 = default_lanes)
+
+int lanes_of(int n, int prec) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  const int l = g_lanes[n][prec == 32 ? 0 : 1];
+  return l ? l : default_lanes(n, prec);
+}
 
 Shape default_shape(int n) {
   static const int iters[13] = {0, 0, 0, 0, 8, 6, 4, 3, 2, 1, 1, 1, 1};
@@ -205,6 +218,44 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
 
 int from_hip(hipError_t e) { return e == hipSuccess ? BG_OK : BG_EHIP; }
 
+// Inverse-CDF tables of the parton density (layout at pdf_sample): built on the host the
+// first time a (pdf_a, pdf_b, tau) triple is used on a device, copied to device memory and
+// kept, immutable, until the process ends (10.5 KB each).
+int pdf_table(const PdfParams& P, const double** out) {
+  struct Entry {
+    int dev;
+    double a, tau;
+    int b;
+    double* d;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BG_EHIP;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const Entry& e : cache)
+    if (e.dev == dev && e.a == P.a && e.b == P.b && e.tau == P.tau) {
+      *out = e.d;
+      return BG_OK;
+    }
+  std::vector<double> h((size_t)kPdfSegs * 4);
+  for (int seg = 0; seg < kPdfSegs; ++seg) pdf_table_segment(P, seg, h.data() + 4 * seg);
+  for (double v : h)
+    if (!std::isfinite(v)) return BG_EINVAL;
+  double* d = nullptr;
+  if (hipMalloc((void**)&d, h.size() * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return BG_ENOMEM;
+  }
+  if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return BG_EHIP;
+  }
+  cache.push_back(Entry{dev, P.a, P.tau, P.b, d});
+  *out = d;
+  return BG_OK;
+}
+
 // Stream-ordered device workspace, released on the stream when the owner goes out of scope.
 struct Workspace {
   double* p = nullptr;
@@ -307,6 +358,23 @@ int bg_set_launch(int n, int prec, int block, int tile_iters) {
   return BG_OK;
 }
 
+int bg_set_lanes(int n, int prec, int lanes) {
+  const Launchers* L = table(n, prec);
+  if (!L) return BG_ENOTSUP;
+  if (lanes != 0 && lanes != 1 && lanes != 2) return BG_EINVAL;
+  if (lanes == 2 && !(L->generate2 && L->amp2_2)) return BG_ENOTSUP;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_lanes[n][prec == 32 ? 0 : 1] = lanes;
+  return BG_OK;
+}
+
+int bg_get_lanes(int n, int prec, int* lanes) {
+  if (!table(n, prec)) return BG_ENOTSUP;
+  if (!lanes) return BG_EINVAL;
+  *lanes = lanes_of(n, prec);
+  return BG_OK;
+}
+
 int bg_get_launch(int n, int prec, int* block, int* tile_iters) {
   if (!table(n, prec)) return BG_ENOTSUP;
   if (!block || !tile_iters) return BG_EINVAL;
@@ -325,26 +393,11 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
     if (st != BG_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
-  // inverse-CDF tables of the classes that sample x1, x2: one stream-ordered workspace,
-  // released (stream-ordered) on every return path
-  Workspace tabs{nullptr, s};
-  {
-    int ntab = 0;
-    for (int k = 0; k < ncfg; ++k) ntab += (G[k].use_pdf && !G[k].in_x && G[k].count > 0) ? 1 : 0;
-    if (ntab > 0) {
-      if (hipMallocAsync((void**)&tabs.p, (size_t)ntab * kPdfSegs * 4 * sizeof(double), s) != hipSuccess) {
-        (void)hipGetLastError();
-        tabs.p = nullptr;
-        return BG_ENOMEM;
-      }
-      int j = 0;
-      for (int k = 0; k < ncfg; ++k) {
-        if (!(G[k].use_pdf && !G[k].in_x && G[k].count > 0)) continue;
-        G[k].pdf.tab = tabs.p + (size_t)j++ * kPdfSegs * 4;
-        const int st = from_hip(launch_pdf_table(G[k].pdf, const_cast<double*>(G[k].pdf.tab), s));
-        if (st != BG_OK) return st;
-      }
-    }
+  // inverse-CDF tables of the classes that sample x1, x2
+  for (int k = 0; k < ncfg; ++k) {
+    if (!(G[k].use_pdf && !G[k].in_x && G[k].count > 0)) continue;
+    const int st = pdf_table(G[k].pdf, &G[k].pdf.tab);
+    if (st != BG_OK) return st;
   }
   const int mode = ncfg > 1 ? g_mixed_mode.load() : kSequential;
   // persistent mode: the FP32 classes in one launch; FP64 classes run their single-class
@@ -370,12 +423,16 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   int64_t nblocks[16];
   size_t off[16];
   size_t bytes = 0;
+  int lanes[16];
   for (int k : todo) {
-    if (!table(cfgs[k].n, cfgs[k].prec)->generate) return BG_ENOTSUP;
-    block[k] = lds_span_table(cfgs[k].n, cfgs[k].prec) ? kLdsLanes : shape_of(cfgs[k].n, cfgs[k].prec).block;
-    nblocks[k] = (G[k].count + block[k] - 1) / block[k];
+    const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
+    lanes[k] = lanes_of(cfgs[k].n, cfgs[k].prec);
+    if (!(lanes[k] == 2 ? L->generate2 : L->generate)) return BG_ENOTSUP;
+    block[k] = (lanes[k] == 1 && lds_span_table(cfgs[k].n, cfgs[k].prec)) ? kLdsLanes
+                                                                           : shape_of(cfgs[k].n, cfgs[k].prec).block;
+    nblocks[k] = (lanes[k] * G[k].count + block[k] - 1) / block[k];
     off[k] = bytes;
-    if (outs[k].acc) bytes += (size_t)nblocks[k] * 4 * sizeof(double);
+    if (outs[k].acc) bytes += ((size_t)nblocks[k] + kFinalizeGroups) * 4 * sizeof(double);
   }
   Workspace parts{nullptr, s};
   if (bytes > 0 && hipMallocAsync((void**)&parts.p, bytes, s) != hipSuccess) {
@@ -385,8 +442,10 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   }
   auto run_class = [&](int k, hipStream_t t) {
     double* partials = outs[k].acc ? parts.p + off[k] / sizeof(double) : nullptr;
-    int st = from_hip(table(cfgs[k].n, cfgs[k].prec)->generate(G[k], partials, block[k], t));
-    if (st == BG_OK && partials) st = from_hip(launch_finalize(partials, nblocks[k], outs[k].acc, t));
+    const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
+    int st = from_hip((lanes[k] == 2 ? L->generate2 : L->generate)(G[k], partials, block[k], t));
+    if (st == BG_OK && partials)
+      st = from_hip(launch_finalize(partials, nblocks[k], partials + 4 * nblocks[k], outs[k].acc, t));
     return st;
   };
   if (mode != kConcurrent || todo.size() < 2) {
@@ -442,7 +501,9 @@ int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, 
   if (N == 0) return BG_OK;
   if (!mom || !hel || !order || !amp2_out) return BG_EINVAL;
   const Shape sh = shape_of(n, prec);
-  return from_hip(L->amp2(N, mom, hel, order, amp2_out, sh.block, (hipStream_t)stream));
+  const Amp2Fn f = lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2;
+  if (!f) return BG_ENOTSUP;
+  return from_hip(f(N, mom, hel, order, amp2_out, sh.block, (hipStream_t)stream));
 }
 
 int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const double* x12, const uint32_t* hel,

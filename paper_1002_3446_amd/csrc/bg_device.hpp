@@ -119,6 +119,7 @@ __device__ __forceinline__ uint64_t shuffle_order(const EventRng& rng) {
 // mantissa), which resolves the (1 - u)^(1/(b+1)) behaviour of x near 1.  Each segment
 // holds the cubic Hermite interpolant of x in the local coordinate theta in [0, 1), from
 // x and dx/dtheta = (Z / f(x)) du/dtheta at its ends; the ends are solved by pdf_solve.
+// The host builds the table once per (a, b, tau) and device.
 // ----------------------------------------------------------------------------------------
 constexpr int kPdfLowSeg = 64;
 constexpr int kPdfBinades = 32;  // s in [2^-33, 2^-1)
@@ -130,28 +131,28 @@ struct PdfParams {
   double usplit, xsplit;
   double coef[17];
   int b;
-  const double* tab;  // [kPdfSegs][4] cubic coefficients, filled by k_pdf_table
+  const double* tab;  // [kPdfSegs][4] cubic coefficients (device memory)
 };
 
-__device__ __forceinline__ double ipow(double x, int k) {
+__host__ __device__ inline double ipow(double x, int k) {
   double r = 1.0;
   for (int i = 0; i < k; ++i) r *= x;
   return r;
 }
 
-__device__ __forceinline__ double pdf_poly(const PdfParams& P, double x) {
+__host__ __device__ inline double pdf_poly(const PdfParams& P, double x) {
   double poly = P.coef[P.b];
   for (int k = P.b - 1; k >= 0; --k) poly = fma(poly, x, P.coef[k]);
   return poly;
 }
 
-// Robust solve of one table node (setup only).  Newton's method in variables where the
+// Robust solve of one table node (table setup only).  Newton's method in variables where the
 // equation is nearly linear:
 //   x < x_split (u < u_split):  log(F(x) - F(tau)) = log(u Z)        in y = log x,
 //                               then one plain Newton step in x (x close to tau);
 //   x >= x_split:               log(F(1) - F(x))   = log((1 - u) Z)  in z = log(1 - x);
 // s = 1 - u is passed exactly.  Converges in 3..7 steps; at most 40.
-__device__ inline double pdf_solve(double u, double s, const PdfParams& P) {
+__host__ __device__ inline double pdf_solve(double u, double s, const PdfParams& P) {
   if (u <= 0.0) return P.tau;
   const double ap1 = P.a + 1.0;
   const bool lower = u < P.usplit;
@@ -212,7 +213,7 @@ __device__ __forceinline__ int pdf_segment(double u, double& theta) {
 }
 
 // u of a segment's local coordinate (the inverse of pdf_segment), with s = 1 - u exact
-__device__ __forceinline__ void pdf_node(int seg, double theta, double& u, double& s, double& dudtheta) {
+__host__ __device__ inline void pdf_node(int seg, double theta, double& u, double& s, double& dudtheta) {
   if (seg < kPdfLowSeg) {
     u = (seg + theta) / (2 * kPdfLowSeg);
     s = 1.0 - u;
@@ -255,8 +256,8 @@ __device__ __forceinline__ double pdf_sample(double u, const PdfParams& P) {
   return x;
 }
 
-// Table setup: one thread per segment.
-__device__ __forceinline__ void pdf_table_segment(const PdfParams& P, int seg, double* out) {
+// One segment of the table (host side, once per density and device).
+__host__ __device__ inline void pdf_table_segment(const PdfParams& P, int seg, double* out) {
   double u0, s0, du0, u1, s1, du1;
   pdf_node(seg, 0.0, u0, s0, du0);
   pdf_node(seg, 1.0, u1, s1, du1);

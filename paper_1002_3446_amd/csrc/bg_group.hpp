@@ -1,0 +1,251 @@
+// The recursion of Eqs. 3.1-3.2 and the closure of Eq. 3.6 with one event spread over G
+// adjacent lanes of a wave (G = 2 or 4; the one-lane form is bg_amplitude).
+//
+// Lane g of a group holds the Lorentz components mu = g C .. g C + C - 1 (C = 4 / G) of
+// every current and span scalar's share, so a lane needs about 1/G of the registers of
+// the one-lane form; at n >= 10 in FP32 and n >= 7 in FP64 the one-lane form exceeds the
+// 512 registers a lane can address and spills to scratch memory.  Minkowski products are
+// formed per lane over its components with their metric signs sigma_mu = (+,-,-,-) and
+// completed across the group by DPP lane permutations; every lane of the group ends with
+// the bitwise same total (IEEE addition is commutative), so the group stays consistent.
+//
+// Span momenta enter covariantly, K_mu = sigma_mu K^mu: the FP64 leg momenta are signed
+// once per event, so J.K needs no signs, and the K-dependent part of a bracket is summed
+// covariantly and converted to contravariant once per span.  K^2 is the group sum of the
+// lanes' FP64 partials sigma_mu K_mu^2.
+#pragma once
+
+#include "bg_device.hpp"
+
+namespace bgk {
+
+template <typename T, int C>
+struct cvl {
+  T re[C], im[C];
+};
+
+// DPP quad permutations: swap neighbouring lanes, swap neighbouring lane pairs
+constexpr int kDppSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppSwap2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
+// (old value 0 with bound_ctrl: the FP32 form folds into v_add_f32_dpp)
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the G lanes of a group; every lane receives the same total.  (Kept apart from
+// neighbouring products so that the FP32 add takes its operand through DPP.)
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T x) {
+#pragma clang fp contract(off)
+  if constexpr (G >= 2) x = x + dpp_mov<kDppSwap1>(x);
+  if constexpr (G >= 4) x = x + dpp_mov<kDppSwap2>(x);
+  return x;
+}
+
+// This lane's share of a group: its first component and the metric signs of its components.
+template <int G, typename T>
+struct LaneShare {
+  static constexpr int C = 4 / G;
+  int mu0;     // first component held
+  T sg[C];     // sigma of each held component
+  __device__ __forceinline__ explicit LaneShare(int g) : mu0(g * C) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) sg[c] = (mu0 + c == 0) ? T(1) : T(-1);
+  }
+  // the held components of a full four-vector (selects, no dynamic register indexing)
+  template <typename U>
+  __device__ __forceinline__ U pick(const U (&v)[4], int c) const {
+    U r = v[c];
+#pragma unroll
+    for (int q = 1; q < G; ++q) r = (mu0 == q * C) ? v[q * C + c] : r;
+    return r;
+  }
+};
+
+// x.y over the group (bilinear, metric (+,-,-,-))
+template <int G, typename T, int C>
+__device__ __forceinline__ void cdot_g(const LaneShare<G, T>& ls, const cvl<T, C>& x, const cvl<T, C>& y, T& r,
+                                       T& i) {
+  r = ls.sg[0] * fmac(-x.im[0], y.im[0], x.re[0] * y.re[0]);
+  i = ls.sg[0] * fmac(x.im[0], y.re[0], x.re[0] * y.im[0]);
+#pragma unroll
+  for (int c = 1; c < C; ++c) {
+    r = fmac(ls.sg[c], fmac(-x.im[c], y.im[c], x.re[c] * y.re[c]), r);
+    i = fmac(ls.sg[c], fmac(x.im[c], y.re[c], x.re[c] * y.im[c]), i);
+  }
+  r = group_sum<G>(r);
+  i = group_sum<G>(i);
+}
+
+// x.K over the group for a covariant real K (this lane's components)
+template <int G, typename T, int C>
+__device__ __forceinline__ void rdot_g(const cvl<T, C>& x, const T (&k)[C], T& r, T& i) {
+  r = x.re[0] * k[0];
+  i = x.im[0] * k[0];
+#pragma unroll
+  for (int c = 1; c < C; ++c) {
+    r = fmac(x.re[c], k[c], r);
+    i = fmac(x.im[c], k[c], i);
+  }
+  r = group_sum<G>(r);
+  i = group_sum<G>(i);
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void caxpy_l(T cr, T ci, const cvl<T, C>& y, cvl<T, C>& acc) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    acc.re[c] = fmac(-ci, y.im[c], fmac(cr, y.re[c], acc.re[c]));
+    acc.im[c] = fmac(ci, y.re[c], fmac(cr, y.im[c], acc.im[c]));
+  }
+}
+
+// Covariant span momenta of this lane's components, summed left to right in FP64 over the
+// legs and cast to T; propagators 1/K^2 from the group sum of FP64 partials.
+template <int L, int G, typename T>
+struct SpanKGroup {
+  static constexpr int C = 4 / G;
+  const double (&k)[L][C];   // covariant FP64 leg components held by this lane
+  const double (&sg)[C];     // their metric signs
+  template <int A, int B>
+  __device__ __forceinline__ void sum(double d[C]) const {
+#pragma unroll
+    for (int c = 0; c < C; ++c) d[c] = k[A][c];
+    static_for<A + 1, B + 1>([&](auto t) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) d[c] += k[decltype(t)::value][c];
+    });
+  }
+  template <int A, int B>
+  __device__ __forceinline__ void K(T (&out)[C]) const {
+    double d[C];
+    sum<A, B>(d);
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = T(d[c]);
+  }
+  template <int A, int B>
+  __device__ __forceinline__ T prop() const {
+    double d[C];
+    sum<A, B>(d);
+    double part;
+    {
+#pragma clang fp contract(off)
+      part = sg[0] * (d[0] * d[0]);
+#pragma unroll
+      for (int c = 1; c < C; ++c) part = part + sg[c] * (d[c] * d[c]);
+    }
+    const double k2 = group_sum<G>(part);
+    if constexpr (std::is_same<T, float>::value)
+      return __builtin_amdgcn_rcpf(float(k2));
+    else
+      return 1.0 / k2;
+  }
+};
+
+// One span [A..B]: its bracket sum V (contravariant, this lane's components).
+template <int L, int A, int B, int G, typename T, typename KS>
+__device__ __forceinline__ void span_vertex_g(const LaneShare<G, T>& ls, const KS& ks,
+                                              const cvl<T, 4 / G> (&J)[Spans<L>::count],
+                                              const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
+                                              cvl<T, 4 / G>& V, T& sr, T& si) {
+  constexpr int C = 4 / G;
+  using SP = Spans<L>;
+  cvl<T, C> X, Z, Yc;  // (J.K) J terms, S terms (contravariant); d (K_A - K_B) (covariant)
+#pragma unroll
+  for (int c = 0; c < C; ++c) X.re[c] = X.im[c] = Z.re[c] = Z.im[c] = Yc.re[c] = Yc.im[c] = T(0);
+  sr = T(0);
+  si = T(0);
+  static_for<A, B>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int PA = SP::at(A, i), PB = SP::at(i + 1, B);
+    T ka[C], kb[C];
+    ks.template K<A, i>(ka);
+    ks.template K<i + 1, B>(kb);
+    T dr, di, ar, ai, br, bi;
+    cdot_g<G>(ls, J[PA], J[PB], dr, di);
+    rdot_g<G>(J[PA], kb, ar, ai);
+    rdot_g<G>(J[PB], ka, br, bi);
+    caxpy_l(ar, ai, J[PB], X);
+    caxpy_l(-br, -bi, J[PA], X);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const T dk = ka[c] - kb[c];
+      Yc.re[c] = fmac(dr, dk, Yc.re[c]);
+      Yc.im[c] = fmac(di, dk, Yc.im[c]);
+    }
+    sr += dr;
+    si += di;
+  });
+  static_for<A, B - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    static_for<i + 1, B>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      T dr, di;
+      cdot_g<G>(ls, J[SP::at(A, i)], J[SP::at(j + 1, B)], dr, di);
+      caxpy_l(dr, di, J[SP::at(i + 1, j)], X);
+    });
+  });
+  static_for<A + 1, B>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    constexpr int Sx = SP::at(A, j);
+    caxpy_l(-Sr[Sx], -Si[Sx], J[SP::at(j + 1, B)], Z);
+  });
+  static_for<A, B - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int Sx = SP::at(i + 1, B);
+    caxpy_l(-Sr[Sx], -Si[Sx], J[SP::at(A, i)], Z);
+  });
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    V.re[c] = fmac(T(2), X.re[c], fmac(ls.sg[c], Yc.re[c], Z.re[c]));
+    V.im[c] = fmac(T(2), X.im[c], fmac(ls.sg[c], Yc.im[c], Z.im[c]));
+  }
+}
+
+// Forward recursion and closure m = eps0 . V[0..L-1] (every lane of the group gets m).
+template <int L, int G, typename T, typename KS>
+__device__ __forceinline__ void bg_amplitude_g(const LaneShare<G, T>& ls, const KS& ks,
+                                               const cvl<T, 4 / G> (&src)[L], const cvl<T, 4 / G>& eps0,
+                                               double& m_re, double& m_im) {
+  constexpr int C = 4 / G;
+  using SP = Spans<L>;
+  cvl<T, C> J[SP::count];
+  T Sr[SP::count], Si[SP::count];
+  static_for<0, L>([&](auto ac) { J[decltype(ac)::value] = src[decltype(ac)::value]; });
+  static_for<2, L>([&](auto lc) {
+    constexpr int len = decltype(lc)::value;
+    static_for<0, L - len + 1>([&](auto ac) {
+      constexpr int a = decltype(ac)::value, b = a + len - 1, s = SP::at(a, b);
+      cvl<T, C> V;
+      T sr, si;
+      span_vertex_g<L, a, b, G, T>(ls, ks, J, Sr, Si, V, sr, si);
+      const T prop = ks.template prop<a, b>();
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        J[s].re[c] = V.re[c] * prop;
+        J[s].im[c] = V.im[c] * prop;
+      }
+      Sr[s] = sr;
+      Si[s] = si;
+    });
+  });
+  cvl<T, C> V;
+  T sr, si;
+  span_vertex_g<L, 0, L - 1, G, T>(ls, ks, J, Sr, Si, V, sr, si);
+  T mr, mi;
+  cdot_g<G>(ls, eps0, V, mr, mi);
+  m_re = double(mr);
+  m_im = double(mi);
+}
+
+}  // namespace bgk

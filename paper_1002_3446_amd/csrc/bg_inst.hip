@@ -20,6 +20,16 @@ using Real = float;
 using Real = double;
 #endif
 
+// the two-lane forms, for the multiplicities of has_lane_pairs
+#if (BG_PREC == 32 && BG_N >= 9) || (BG_PREC == 64 && BG_N >= 6)
+#define BG_PAIRS 1
+#else
+#define BG_PAIRS 0
+#endif
+static_assert(has_lane_pairs(BG_N, BG_PREC) == (BG_PAIRS == 1), "lane-pair build condition");
+
+// Launchers take the workgroup size chosen by the host (which also sizes the partials:
+// one per workgroup, ceil(count * lanes / block) workgroups).
 #if BG_KIND == 0
 hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
                                                               hipStream_t s) {
@@ -28,6 +38,14 @@ hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C,
   hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, C, partials);
   return hipGetLastError();
 }
+#if BG_PAIRS
+hipError_t BG_NAME(launch_generate2_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
+                                                               hipStream_t s) {
+  const int64_t nb = (2 * C.count + block - 1) / block;
+  hipLaunchKernelGGL((k_generate_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, C, partials);
+  return hipGetLastError();
+}
+#endif
 #elif BG_KIND == 1
 hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
                                                           const uint8_t* order, double* out, int block,
@@ -37,6 +55,15 @@ hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const d
   hipLaunchKernelGGL((k_amp2<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
   return hipGetLastError();
 }
+#if BG_PAIRS
+hipError_t BG_NAME(launch_amp2_2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
+                                                            const uint8_t* order, double* out, int block,
+                                                            hipStream_t s) {
+  const int64_t nb = (2 * count + block - 1) / block;
+  hipLaunchKernelGGL((k_amp2_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
+  return hipGetLastError();
+}
+#endif
 #elif BG_KIND == 2
 hipError_t BG_NAME(launch_grad_n, BG_N, BG_PREC, BG_KIND)(const GradArgs& G, int block, hipStream_t s) {
   const int64_t nb = (G.count + block - 1) / block;

@@ -5,6 +5,7 @@
 #include <type_traits>
 
 #include "bg_device.hpp"
+#include "bg_group.hpp"
 #include "bg_launch.hpp"
 #include "bg_params.hpp"
 
@@ -22,9 +23,9 @@ struct EventKin {
 };
 
 // Builds an event's phase-space point (Sec. 3: RAMBO then the longitudinal boost) from
-// Philox draws or from caller inputs; writes the optional draw outputs.
+// Philox draws or from caller inputs; writes the optional draw outputs when store is set.
 template <int N>
-__device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventKin<N>& ev) {
+__device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventKin<N>& ev, bool store = true) {
   constexpr int NF = N - 2;
   const uint64_t e = C.first_event + (uint64_t)i;
   EventRng rng{(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)N, C.key0, C.key1};
@@ -89,7 +90,7 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
     if (out) {
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) Q[mu] += q[t][mu];
-      if (C.out.uniforms) {
+      if (store && C.out.uniforms) {
         double* uo = C.out.uniforms + (i * NF + pidx) * 4;
         uo[0] = r[0]; uo[1] = r[1]; uo[2] = r[2]; uo[3] = r[3];
       }
@@ -119,6 +120,7 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
       ev.pc[t][mu] = pc[mu];
     }
   }
+  if (!store) return;
   if (C.out.hel) C.out.hel[i] = ev.hel;
   if (C.out.order) {
 #pragma unroll
@@ -233,6 +235,46 @@ __device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const ui
   return ldexp(mr * mr + mi * mi, 2 * ex * (4 - N) - (N - 2));
 }
 
+// The same with the event spread over the G lanes of a group; g is this lane's place in it.
+template <int N, typename T, int G>
+__device__ __forceinline__ double ordered_amp2_g(const double (&p)[N][4], const uint32_t (&leg)[N], uint32_t hel,
+                                                 int g) {
+  constexpr int C = 4 / G;
+  double esum = 0.0;
+#pragma unroll
+  for (int t = 0; t < N; ++t) esum += fabs(p[t][0]);
+  const int ex = ilogb(0.5 * esum);
+  const double sc = ldexp(1.0, -ex);
+  const LaneShare<G, T> ls(g);
+  const LaneShare<G, double> lsd(g);
+  double k[N - 1][C];  // covariant, this lane's components
+  cvl<T, C> src[N - 1], e0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double sg = leg[t] < 2u ? -sc : sc;
+#pragma unroll
+    for (int c = 0; c < C; ++c) k[t - 1][c] = lsd.sg[c] * (sg * lsd.pick(p[t], c));
+    const cv4<T> e = polarisation<T>(p[t], (hel >> leg[t]) & 1u);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      src[t - 1].re[c] = ls.pick(e.re, c);
+      src[t - 1].im[c] = ls.pick(e.im, c);
+    }
+  }
+  {
+    const cv4<T> e = polarisation<T>(p[0], (hel >> leg[0]) & 1u);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      e0.re[c] = ls.pick(e.re, c);
+      e0.im[c] = ls.pick(e.im, c);
+    }
+  }
+  SpanKGroup<N - 1, G, T> ks{k, lsd.sg};
+  double mr, mi;
+  bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
+  return ldexp(mr * mr + mi * mi, 2 * ex * (4 - N) - (N - 2));
+}
+
 // Compensated (sum w, sum w^2) of a workgroup of up to 256 lanes, in a fixed tree order;
 // thread 0 stores (s, c, s2, c2) to dst.
 __device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst) {
@@ -261,14 +303,22 @@ __device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst)
 }
 
 // One event: draws -> kinematics -> cuts -> |A|^2 -> weight; writes outputs; returns w.
-template <int N, typename T, bool LDS = false>
-__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, LdsTable<N>* tab = nullptr) {
+// With G > 1 lanes per event every lane of the group evaluates the kinematics (the same
+// values), the recursion is shared, and lane g = 0 writes the outputs and returns w
+// (the others return 0).
+template <int N, typename T, bool LDS = false, int G = 1>
+__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, LdsTable<N>* tab = nullptr, int g = 0) {
   EventKin<N> ev;
-  build_event<N>(C, i, ev);
+  build_event<N>(C, i, ev, g == 0);
   double ht, rmin;
   const bool pass = cuts<N>(C, ev, ht, rmin);
   // |A|^2 is Lorentz invariant: evaluated in the partonic centre-of-mass frame
-  const double a2 = ordered_amp2<N, T, LDS>(ev.pc, ev.leg, ev.hel, tab);
+  double a2;
+  if constexpr (G == 1)
+    a2 = ordered_amp2<N, T, LDS>(ev.pc, ev.leg, ev.hel, tab);
+  else
+    a2 = ordered_amp2_g<N, T, G>(ev.pc, ev.leg, ev.hel, g);
+  if (g != 0) return 0.0;
   double sp = 1.0;
 #pragma unroll
   for (int k = 0; k < (N > 5 ? N - 5 : 5 - N); ++k) sp *= ev.shat;
@@ -330,6 +380,40 @@ __global__ __launch_bounds__((UseLdsK<N, T>::value ? kLdsLanes : 256)) __attribu
   } else {
     out[i] = ordered_amp2<N, T, false>(p, leg, hel[i], nullptr);
   }
+}
+
+// Single-class generation with G lanes per event (blockDim.x a multiple of 64, at most 256):
+// events blockIdx.x * blockDim.x / G + threadIdx.x / G.
+template <int N, typename T, int G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate_g(GenClass C,
+                                                                                              double* partials) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int g = (int)(threadIdx.x % G);
+  double w = 0.0;
+  if (i < C.count) w = generate_one<N, T, false, G>(C, i, nullptr, g);
+  if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
+}
+
+// bg_amp2 with G lanes per event.
+template <int N, typename T, int G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_amp2_g(
+    int64_t count, const double* __restrict__ mom, const uint32_t* __restrict__ hel, const uint8_t* __restrict__ order,
+    double* __restrict__ out) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int g = (int)(threadIdx.x % G);
+  if (i >= count) return;
+  double p[N][4];
+  uint32_t leg[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    const uint32_t l = order[i * N + t];
+    leg[t] = l < (uint32_t)N ? l : (uint32_t)(N - 1);  // malformed input stays in bounds
+    const double* q = mom + (i * N + leg[t]) * 4;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) p[t][mu] = q[mu];
+  }
+  const double a2 = ordered_amp2_g<N, T, G>(p, leg, hel[i], g);
+  if (g == 0) out[i] = a2;
 }
 
 }  // namespace bgk

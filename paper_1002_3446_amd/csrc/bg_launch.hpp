@@ -15,6 +15,12 @@ namespace bgk {
 constexpr int kLdsLanes = 64;
 constexpr bool lds_span_table(int n, int prec) { return prec == 32 && n <= 8; }
 
+// Multiplicities whose kernels are also built with an event spread over two lanes (the
+// one-lane recursion needs more than 512 registers there); which form runs is a launch
+// setting (bg_set_lanes), defaulting to default_lanes.
+constexpr bool has_lane_pairs(int n, int prec) { return prec == 32 ? n >= 9 : n >= 6; }
+constexpr int default_lanes(int n, int prec) { return prec == 32 ? (n >= 10 ? 2 : 1) : (n >= 7 ? 2 : 1); }
+
 struct GradArgs {
   int64_t count;
   double sqrt_s;
@@ -41,12 +47,15 @@ struct Launchers {
   GenerateFn generate;
   Amp2Fn amp2;
   GradFn grad;
+  GenerateFn generate2;  // two lanes per event (where has_lane_pairs)
+  Amp2Fn amp2_2;
 };
 
-hipError_t launch_finalize(const double* partials, int64_t nparts, double* acc, hipStream_t s);
-
-// Fills tab[kPdfSegs][4] (device) with the inverse-CDF table of P's density.
-hipError_t launch_pdf_table(const PdfParams& P, double* tab, hipStream_t s);
+// Fixed-order compensated reduction of nparts partials into acc, through level2
+// (kFinalizeGroups x 4 doubles of scratch): at most kFinalizeGroups workgroups reduce
+// contiguous runs of partials, then one workgroup adds their results to acc.
+constexpr int kFinalizeGroups = 512;
+hipError_t launch_finalize(const double* partials, int64_t nparts, double* level2, double* acc, hipStream_t s);
 
 // One class of a multi-class launch and one tile of its work list (device-resident).
 struct MultiClass {

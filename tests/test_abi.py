@@ -66,5 +66,16 @@ def test_host_error_paths():
     assert lib.bg_set_mixed_launch(2) == bg.BG_OK and lib.bg_get_mixed_launch() == 2
     assert lib.bg_set_mixed_launch(0) == bg.BG_OK and lib.bg_get_mixed_launch() == 0
     assert lib.bg_set_mixed_launch(1) == bg.BG_OK and lib.bg_get_mixed_launch() == 1
+    v = ctypes.c_int()
+    assert lib.bg_set_lanes(8, 32, 3) == bg.BG_EINVAL
+    assert lib.bg_set_lanes(3, 32, 1) == bg.BG_ENOTSUP
+    assert lib.bg_get_lanes(8, 32, None) == bg.BG_EINVAL
+    keep = {n: bg.get_lanes(n, 32) for n in (8, 12)}
+    assert lib.bg_set_lanes(8, 32, 0) == bg.BG_OK and lib.bg_set_lanes(12, 32, 0) == bg.BG_OK
+    assert lib.bg_get_lanes(8, 32, ctypes.byref(v)) == bg.BG_OK and v.value == 1    # defaults
+    assert lib.bg_get_lanes(12, 32, ctypes.byref(v)) == bg.BG_OK and v.value == 2
+    assert lib.bg_set_lanes(8, 32, 2) == bg.BG_ENOTSUP   # no two-lane form at n = 8 FP32
+    for n, l in keep.items():
+        bg.set_lanes(n, 32, l)
     b, k = ctypes.c_int(), ctypes.c_int()
     assert lib.bg_get_launch(8, 32, ctypes.byref(b), ctypes.byref(k)) == bg.BG_OK and b.value in (64, 128, 192, 256)

@@ -1,4 +1,7 @@
-"""GPU parity of bg_amp2 (recursion + closure on given momenta) against the oracle."""
+"""GPU parity of bg_amp2 (recursion + closure on given momenta) against the oracle, for
+the one-lane and (where built) the two-lane form of the recursion."""
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -8,6 +11,21 @@ from paper_1002_3446_amd import inputs
 from tests.parity import check_amp2_fp64, fp32_errors
 
 pytestmark = pytest.mark.gpu
+
+
+def lane_forms(n, prec):
+    """Lanes-per-event forms the library holds for (n, prec)."""
+    return [1, 2] if (prec == 32 and n >= 9) or (prec == 64 and n >= 6) else [1]
+
+
+@contextlib.contextmanager
+def lanes_set(bg, n, prec, lanes):
+    old = bg.get_lanes(n, prec)
+    bg.set_lanes(n, prec, lanes)
+    try:
+        yield
+    finally:
+        bg.set_lanes(n, prec, old)
 
 
 def make_points(n, N, seed, rs=1000.0):
@@ -26,21 +44,25 @@ def run_gpu(bg, n, prec, mom, hel, order):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9, 10, 11, 12])
-def test_amp2_fp64_parity(gpu_lib, n):
+@pytest.mark.parametrize("n,lanes", [(n, l) for n in range(4, 13) for l in lane_forms(n, 64)])
+def test_amp2_fp64_parity(gpu_lib, n, lanes):
     N = 8 * 256 + 37            # several workgroups and a ragged tail
     mom, hel, order = make_points(n, N, 100 + n)
-    print(f"amp2 fp64 n={n} N={N}", flush=True)
-    stats = check_amp2_fp64(run_gpu(gpu_lib, n, 64, mom, hel, order), mom, hel, order)
+    print(f"amp2 fp64 n={n} lanes={lanes} N={N}", flush=True)
+    with lanes_set(gpu_lib, n, 64, lanes):
+        got = run_gpu(gpu_lib, n, 64, mom, hel, order)
+    stats = check_amp2_fp64(got, mom, hel, order)
     print(stats)
 
 
-@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9, 10, 11, 12])
-def test_amp2_fp32_error(gpu_lib, n):
+@pytest.mark.parametrize("n,lanes", [(n, l) for n in range(4, 13) for l in lane_forms(n, 32)])
+def test_amp2_fp32_error(gpu_lib, n, lanes):
     N = 2 * 256 + 11
     mom, hel, order = make_points(n, N, 200 + n)
-    print(f"amp2 fp32 n={n} N={N}", flush=True)
-    rel = fp32_errors(run_gpu(gpu_lib, n, 32, mom, hel, order), mom, hel, order)
+    print(f"amp2 fp32 n={n} lanes={lanes} N={N}", flush=True)
+    with lanes_set(gpu_lib, n, 32, lanes):
+        got = run_gpu(gpu_lib, n, 32, mom, hel, order)
+    rel = fp32_errors(got, mom, hel, order)
     q = np.quantile(rel, [0.5, 0.9, 0.99])
     print(f"n={n} fp32 rel err median {q[0]:.2e} p90 {q[1]:.2e} p99 {q[2]:.2e}")
     assert q[0] <= 1e-4

@@ -123,6 +123,34 @@ def test_pdf_events(gpu_lib, n, prec):
     print(compare_events(g, o, oc, prec))
 
 
+@pytest.mark.parametrize("n,prec", [(7, 64), (9, 32), (12, 32), (10, 64)])
+def test_lane_forms_agree(gpu_lib, n, prec):
+    """bg_generate with one and with two lanes per event: identical draws, kinematics and
+    cut flags; |A|^2 and weights within the recursion precision's rounding (FP64 against
+    the oracle's rules, FP32 as for the persistent kernel)."""
+    c = cfg_c1(gpu_lib, n=n, prec=prec, seed=4242 + n)
+    N = 3 * 256 + 19
+    old = gpu_lib.get_lanes(n, prec)
+    res = {}
+    try:
+        for lanes in (1, 2):
+            gpu_lib.set_lanes(n, prec, lanes)
+            print(f"generate n={n} prec={prec} lanes={lanes}", flush=True)
+            res[lanes] = to_np(gpu_lib.generate(c, N, outputs=ALL))
+    finally:
+        gpu_lib.set_lanes(n, prec, old)
+    one, two = res[1], res[2]
+    for k in ("hel", "order", "pass", "momenta", "obs", "x12", "uniforms"):
+        assert np.array_equal(one[k], two[k]), k
+    oc = oracle_cfg(c)
+    oc["tau_min"] = pdf.tau_min(n, 20.0, 14000.0)
+    print(compare_events(two, event.generate(oc, np.arange(N)), oc, prec))
+    if prec == 32:
+        same_events(two, one, n)
+    exact = math.fsum(two["weight"].tolist())
+    assert abs((two["acc"][0] + two["acc"][1]) - exact) <= 2 * EPS * np.abs(two["weight"]).sum()
+
+
 @pytest.mark.parametrize("n", [4, 8, 12])
 def test_sampler_extreme_uniforms(gpu_lib, n):
     """Parton fractions at the ends of the inverse-CDF table: events whose x1 or x2 word lies
@@ -192,7 +220,7 @@ def test_determinism_split_and_shape(gpu_lib):
         gpu_lib.set_launch(n, 32, 64, 3)
         d = to_np(gpu_lib.generate(c, N, outputs=ALL))
     finally:
-        gpu_lib.set_launch(n, 32, 0, 0)
+        gpu_lib.set_launch(n, 32, *old)
     assert gpu_lib.get_launch(n, 32) == old
     for k in ("weight", "amp2", "momenta", "pass", "obs"):
         assert np.array_equal(d[k], a[k]), k
