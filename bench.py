@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=1 << 24)
+    ap.add_argument("--n", type=int, default=8,
+                    help="multiplicity of the main line (8, the benchmark workload; others for profiling)")
     ap.add_argument("--no-extras", action="store_true", help="main line only (used under profilers)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--recursion", action="store_true",
@@ -249,7 +251,7 @@ def main():
 
     torch.cuda.set_device(0)
     outputs = ("weight", "amp2", "obs", "pass", "acc")
-    n, N = 8, a.events
+    n, N = a.n, a.events
     cfg = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
     wall, ms, out = run_steps(bg, torch, cfg, N, a.steps, a.warmup, outputs)
     ms_step = 1e3 * wall / a.steps
@@ -257,9 +259,10 @@ def main():
     launch_ms = sum(ms) / len(ms)
     fp = flops_plain(n)
     fe = flops_executed(n)
+    kname = f"k_generate<{n},float>" if bg.get_lanes(n, 32) == 1 else f"k_generate_g<{n},float,2>"
     achieved = fp * N / (launch_ms * 1e-3)
     line = {
-        "metric": "events/s at gg->6g (n=8) FP32 recursion (FP64 kinematics and weights), full generation path",
+        "metric": f"events/s at gg->{n - 2}g (n={n}) FP32 recursion (FP64 kinematics and weights), full generation path",
         "value": value,
         "unit": "events/s",
         "n_gpus": 1,
@@ -271,13 +274,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 recursion + f64 kinematics/weights",
         "data": "synthetic: Philox-seeded RAMBO events generated on the device",
-        "config": {"workload": "gg->6g (8 external gluons), 2^24 events per step, sqrt(S)=14 TeV, "
-                               "x ~ x^-1.3 (1-x)^5 on [7.35e-5,1), alpha_s=0.118, random helicity and "
+        "config": {"workload": f"gg->{n - 2}g ({n} external gluons), {N} events per step, sqrt(S)=14 TeV, "
+                               f"x ~ x^-1.3 (1-x)^5 on [{((n - 2) * 20.0 / 14000.0) ** 2:.3g},1), alpha_s=0.118, random helicity and "
                                "colour ordering per event, cuts pT>20 GeV |eta|<2.5 dR>0.4",
                    "n": n, "events_per_step": N, "prec": 32, "parallelism": "one event per lane, 1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": traffic_from_profile("k_generate<8,float>"),
-                     "kernel": "k_generate<8,float>", "launch_ms": launch_ms,
+                     "frac": achieved / PEAK_FP32, "traffic": traffic_from_profile(kname),
+                     "kernel": kname, "launch_ms": launch_ms,
                      "flops_per_event_plain": fp, "flops_per_event_executed": fe,
                      "executed_tflops": fe * N / (launch_ms * 1e-3) / 1e12,
                      "executed_frac": fe * N / (launch_ms * 1e-3) / PEAK_FP32},
