@@ -12,6 +12,7 @@
 // rule is xb += conj(y) wb, and a real factor r of a complex z gets rb += Re(conj(z) wb).
 #pragma once
 
+#include "bg_group_adj.hpp"
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
 
@@ -323,120 +324,114 @@ __device__ __forceinline__ void rambo_q_adj(double r1, double r2, double r3, dou
   rb[3] = -q0b / r4;
 }
 
-// One event: forward (CM momenta, recursion), log w_int, reverse sweep, gradients.
-template <int N, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_grad(GradArgs G) {
-  constexpr int NF = N - 2, L = N - 1;
-  using SP = Spans<L>;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.count) return;
+// Per-event kinematics of the gradient kernels (partonic centre-of-mass frame).
+template <int N>
+struct GradKin {
   uint32_t leg[N];
-  leg[0] = 0;
+  uint32_t hel;
+  double x1, x2, shat, rs;
+  double q[N][4];   // RAMBO's q (position order; beam positions unused)
+  double Q[4];
+  RamboMap map;
+  double pc[N][4];  // physical CM momenta, position order
+  int ex;           // momentum scale 2^-ex of the recursion
+  double sc;
+};
+
+template <int N>
+__device__ __forceinline__ void grad_front(const GradArgs& G, int64_t i, GradKin<N>& K) {
+  constexpr int NF = N - 2;
+  K.leg[0] = 0;
 #pragma unroll
   for (int t = 1; t < N; ++t) {
     const uint32_t l = G.order[i * N + t];
-    leg[t] = l < 1u ? 1u : (l > (uint32_t)(N - 1) ? (uint32_t)(N - 1) : l);
+    K.leg[t] = l < 1u ? 1u : (l > (uint32_t)(N - 1) ? (uint32_t)(N - 1) : l);
   }
-  const uint32_t hel = G.hel[i];
-  double x1 = 1.0, x2 = 1.0, shat = G.sqrt_s * G.sqrt_s, rs = G.sqrt_s;
+  K.hel = G.hel[i];
+  K.x1 = 1.0;
+  K.x2 = 1.0;
+  K.shat = G.sqrt_s * G.sqrt_s;
+  K.rs = G.sqrt_s;
   if (G.use_pdf) {
-    x1 = G.x12[2 * i];
-    x2 = G.x12[2 * i + 1];
-    shat = x1 * x2 * G.sqrt_s * G.sqrt_s;
-    rs = sqrt(shat);
+    K.x1 = G.x12[2 * i];
+    K.x2 = G.x12[2 * i + 1];
+    K.shat = K.x1 * K.x2 * G.sqrt_s * G.sqrt_s;
+    K.rs = sqrt(K.shat);
   }
   // RAMBO in position order (centre-of-mass frame)
-  double q[N][4];
-  double Q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) K.Q[mu] = 0.0;
 #pragma unroll
   for (int t = 1; t < N; ++t) {
-    const bool out = leg[t] >= 2u;
-    const uint32_t pidx = out ? leg[t] - 2u : 0u;
+    const bool out = K.leg[t] >= 2u;
+    const uint32_t pidx = out ? K.leg[t] - 2u : 0u;
     const double* u = G.u + (i * NF + pidx) * 4;
-    rambo_q(u[0], u[1], u[2], u[3], q[t]);
+    rambo_q(u[0], u[1], u[2], u[3], K.q[t]);
     if (out) {
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) Q[mu] += q[t][mu];
+      for (int mu = 0; mu < 4; ++mu) K.Q[mu] += K.q[t][mu];
     }
   }
-  RamboMap map;
-  map.init(Q, rs);
-  double pc[N][4];
+  K.map.init(K.Q, K.rs);
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    map.apply(q[t], pc[t]);
-    if (leg[t] < 2u) {
-      const double zs = leg[t] == 0u ? 0.5 * rs : -0.5 * rs;
-      pc[t][0] = 0.5 * rs; pc[t][1] = 0.0; pc[t][2] = 0.0; pc[t][3] = zs;
+    K.map.apply(K.q[t], K.pc[t]);
+    if (K.leg[t] < 2u) {
+      const double zs = K.leg[t] == 0u ? 0.5 * K.rs : -0.5 * K.rs;
+      K.pc[t][0] = 0.5 * K.rs; K.pc[t][1] = 0.0; K.pc[t][2] = 0.0; K.pc[t][3] = zs;
     }
   }
-  // forward recursion on scaled momenta
   double esum = 0.0;
 #pragma unroll
-  for (int t = 0; t < N; ++t) esum += fabs(pc[t][0]);
-  const int ex = ilogb(0.5 * esum);
-  const double sc = ldexp(1.0, -ex);
-  double k[L][4];
-  cv4<T> src[L];
-#pragma unroll
-  for (int t = 1; t < N; ++t) {
-    const double sg = leg[t] < 2u ? -sc : sc;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) k[t - 1][mu] = sg * pc[t][mu];
-    src[t - 1] = polarisation<T>(pc[t], (hel >> leg[t]) & 1u);
-  }
-  const cv4<T> e0 = polarisation<T>(pc[0], hel & 1u);
-  cv4<T> J[SP::count];
-  T Sr[SP::count], Si[SP::count];
-  cv4<T> V;
-  SpanKLegs<L, T> ks{k};
-  bg_forward<L, T>(ks, src, J, Sr, Si, V);
-  T mr, mi;
-  cdot(e0, V, mr, mi);
-  const double m2 = double(mr) * double(mr) + double(mi) * double(mi);
+  for (int t = 0; t < N; ++t) esum += fabs(K.pc[t][0]);
+  K.ex = ilogb(0.5 * esum);
+  K.sc = ldexp(1.0, -K.ex);
+}
+
+// log w_int from |m|^2 of the scaled momenta; false (and zero gradients written) when
+// |m|^2 vanishes or is not finite.
+template <int N>
+__device__ __forceinline__ bool grad_logw(const GradArgs& G, int64_t i, const GradKin<N>& K, double m2, bool store) {
+  constexpr int NF = N - 2;
   const double ln2 = 0.69314718055994530942;
-  double lw = log(m2) + (double)(2 * ex * (4 - N) - (N - 2)) * ln2 + (N - 5) * log(shat) + G.log_const;
-  if (G.use_pdf) lw += G.pdf_a * (log(x1) + log(x2)) + G.pdf_b * (log1p(-x1) + log1p(-x2));
-  double* gu = G.grad_u + i * NF * 4;
+  double lw = log(m2) + (double)(2 * K.ex * (4 - N) - (N - 2)) * ln2 + (N - 5) * log(K.shat) + G.log_const;
+  if (G.use_pdf) lw += G.pdf_a * (log(K.x1) + log(K.x2)) + G.pdf_b * (log1p(-K.x1) + log1p(-K.x2));
   if (!(m2 > 0.0) || !isfinite(m2)) {
-    for (int c = 0; c < NF * 4; ++c) gu[c] = 0.0;
-    G.grad_x[2 * i] = 0.0;
-    G.grad_x[2 * i + 1] = 0.0;
-    if (G.logw) G.logw[i] = -INFINITY;
-    return;
+    if (store) {
+      double* gu = G.grad_u + i * NF * 4;
+      for (int c = 0; c < NF * 4; ++c) gu[c] = 0.0;
+      G.grad_x[2 * i] = 0.0;
+      G.grad_x[2 * i + 1] = 0.0;
+      if (G.logw) G.logw[i] = -INFINITY;
+    }
+    return false;
   }
-  if (G.logw) G.logw[i] = lw;
+  if (store && G.logw) G.logw[i] = lw;
+  return true;
+}
+
+// From the CM momentum adjoints pb (polarisation adjoints included) and the sqrt(s_hat)
+// adjoint of the beams: RAMBO's conformal map, q(rho), and x1, x2; writes the gradients.
+template <int N>
+__device__ __forceinline__ void grad_back(const GradArgs& G, int64_t i, const GradKin<N>& K, const double (&pb)[N][4],
+                                          double rsb) {
+  constexpr int NF = N - 2;
   const double gw = G.gout ? G.gout[i] : 1.0;
-  // reverse sweep: d log|m|^2 / dm = 2 m / |m|^2
-  cv4<T> srcb[L], e0b;
-  T kb[L][4];
-  bg_reverse<L, T>(k, J, Sr, Si, e0, V, T(2.0 * double(mr) / m2), T(2.0 * double(mi) / m2), srcb, e0b, kb);
-  // momentum adjoints (CM frame)
-  double pb[N][4];
-  double rsb = 0.0;
-#pragma unroll
-  for (int t = 1; t < N; ++t) {
-    const double sg = leg[t] < 2u ? -sc : sc;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) pb[t][mu] = sg * double(kb[t - 1][mu]);
-    if (leg[t] >= 2u) polarisation_adj<T>(pc[t], (hel >> leg[t]) & 1u, srcb[t - 1], pb[t]);
-    else rsb += 0.5 * (pb[t][0] - pb[t][3]);  // leg 1: p = (rs/2)(1, 0, 0, -1)
-  }
-  // RAMBO's conformal map and q(rho)
   RamboMapAdj A{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double qb[N][4];
 #pragma unroll
   for (int t = 1; t < N; ++t) {
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) qb[t][mu] = 0.0;
-    if (leg[t] >= 2u) rambo_apply_adj(map, q[t], pb[t], qb[t], A);
+    if (K.leg[t] >= 2u) rambo_apply_adj(K.map, K.q[t], pb[t], qb[t], A);
   }
   double Qb[4] = {0.0, 0.0, 0.0, 0.0};
-  rambo_init_adj(map, Q, A, Qb, rsb);
+  rambo_init_adj(K.map, K.Q, A, Qb, rsb);
+  double* gu = G.grad_u + i * NF * 4;
 #pragma unroll
   for (int t = 1; t < N; ++t) {
-    if (leg[t] >= 2u) {
-      const uint32_t pidx = leg[t] - 2u;
+    if (K.leg[t] >= 2u) {
+      const uint32_t pidx = K.leg[t] - 2u;
       const double* u = G.u + (i * NF + pidx) * 4;
       double qbt[4], rb[4];
 #pragma unroll
@@ -449,11 +444,224 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   // s_hat = x1 x2 S:  d sqrt(s_hat) / dx_i = sqrt(s_hat) / (2 x_i)
   double xb1 = 0.0, xb2 = 0.0;
   if (G.use_pdf) {
-    xb1 = rsb * rs / (2.0 * x1) + (N - 5) / x1 + G.pdf_a / x1 - G.pdf_b / (1.0 - x1);
-    xb2 = rsb * rs / (2.0 * x2) + (N - 5) / x2 + G.pdf_a / x2 - G.pdf_b / (1.0 - x2);
+    xb1 = rsb * K.rs / (2.0 * K.x1) + (N - 5) / K.x1 + G.pdf_a / K.x1 - G.pdf_b / (1.0 - K.x1);
+    xb2 = rsb * K.rs / (2.0 * K.x2) + (N - 5) / K.x2 + G.pdf_a / K.x2 - G.pdf_b / (1.0 - K.x2);
   }
   G.grad_x[2 * i] = gw * xb1;
   G.grad_x[2 * i + 1] = gw * xb2;
+}
+
+// The recursion's adjoints go to the second kernel (k_grad_back), which takes them through
+// the helicity sources, the momentum scaling, RAMBO and x1, x2: kept in one kernel, those
+// values stay live across the reverse sweep and spill to scratch.  Per position t = 1..N-1
+// twelve words: the contravariant adjoint of the scaled recursion momentum (4), then the
+// source adjoint's real (4) and imaginary (4) parts; then a flag (0: |A|^2 = 0, nothing to
+// do).  Layout [word][event], so neighbouring lanes write neighbouring words.
+template <int N>
+struct GradRaw {
+  static constexpr int words = 12 * (N - 1) + 1;
+  __host__ __device__ static constexpr int at(int t, int w) { return 12 * (t - 1) + w; }
+};
+
+// One event per lane: forward (CM momenta, recursion), log w_int, reverse sweep, momentum
+// adjoints.
+template <int N, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_grad(GradArgs G) {
+  constexpr int L = N - 1;
+  using SP = Spans<L>;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.count) return;
+  GradKin<N> K;
+  grad_front<N>(G, i, K);
+  double k[L][4];
+  cv4<T> src[L];
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double sg = K.leg[t] < 2u ? -K.sc : K.sc;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) k[t - 1][mu] = sg * K.pc[t][mu];
+    src[t - 1] = polarisation<T>(K.pc[t], (K.hel >> K.leg[t]) & 1u);
+  }
+  const cv4<T> e0 = polarisation<T>(K.pc[0], K.hel & 1u);
+  cv4<T> J[SP::count];
+  T Sr[SP::count], Si[SP::count];
+  cv4<T> V;
+  SpanKLegs<L, T> ks{k};
+  bg_forward<L, T>(ks, src, J, Sr, Si, V);
+  T mr, mi;
+  cdot(e0, V, mr, mi);
+  const double m2 = double(mr) * double(mr) + double(mi) * double(mi);
+  if (!grad_logw<N>(G, i, K, m2, true)) {
+    G.pbuf[(GradRaw<N>::words - 1) * G.count + i] = 0.0;  // nothing for the second kernel
+    return;
+  }
+  // reverse sweep: d log|m|^2 / dm = 2 m / |m|^2
+  cv4<T> srcb[L], e0b;
+  T kb[L][4];
+  bg_reverse<L, T>(k, J, Sr, Si, e0, V, T(2.0 * double(mr) / m2), T(2.0 * double(mi) / m2), srcb, e0b, kb);
+  double* o = G.pbuf + i;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      o[GradRaw<N>::at(t, mu) * G.count] = double(kb[t - 1][mu]);
+      o[GradRaw<N>::at(t, 4 + mu) * G.count] = double(srcb[t - 1].re[mu]);
+      o[GradRaw<N>::at(t, 8 + mu) * G.count] = double(srcb[t - 1].im[mu]);
+    }
+  }
+  o[(GradRaw<N>::words - 1) * G.count] = 1.0;
+}
+
+// LDS words per lane that hold the forward values of the two-lane gradient kernel: currents
+// 4 words each, span scalars 2 (spans of two or more legs), the closure's bracket 4.
+template <int N>
+struct GradStage {
+  static constexpr int slots = Spans<N - 1>::count * 4 + (Spans<N - 1>::count - (N - 1)) * 2 + 4;
+};
+
+// Two lanes per event (the grouped recursion and its reverse sweep, bg_group_adj.hpp); both
+// lanes evaluate the kinematics and the momentum adjoints, lane 0 writes.  FP32 with n <= 8
+// (the forward values are staged in LDS, 632 B per lane at n = 8), workgroups of 256 lanes.
+template <int N, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_grad_g(GradArgs G) {
+  constexpr int L = N - 1, GL = 2, C = 2;
+  using SP = Spans<L>;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL;
+  const int g = (int)(threadIdx.x % GL);
+  if (i >= G.count) return;
+  GradKin<N> K;
+  grad_front<N>(G, i, K);
+  const LaneShare<GL, T> ls(g);
+  const LaneShare<GL, double> lsd(g);
+  double k[L][C];  // covariant, this lane's components
+  cvl<T, C> src[L], e0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double sg = K.leg[t] < 2u ? -K.sc : K.sc;
+#pragma unroll
+    for (int c = 0; c < C; ++c) k[t - 1][c] = lsd.sg[c] * (sg * lsd.pick(K.pc[t], c));
+    const cv4<T> e = polarisation<T>(K.pc[t], (K.hel >> K.leg[t]) & 1u);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      src[t - 1].re[c] = ls.pick(e.re, c);
+      src[t - 1].im[c] = ls.pick(e.im, c);
+    }
+  }
+  {
+    const cv4<T> e = polarisation<T>(K.pc[0], K.hel & 1u);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      e0.re[c] = ls.pick(e.re, c);
+      e0.im[c] = ls.pick(e.im, c);
+    }
+  }
+  SpanKGroup<L, GL, T> ks{k, lsd.sg};
+  cvl<T, C> J[SP::count];
+  T Sr[SP::count], Si[SP::count];
+  cvl<T, C> V;
+  bg_forward_g<L, GL, T>(ls, ks, src, J, Sr, Si, V);
+  T mr, mi;
+  cdot_g<GL>(ls, e0, V, mr, mi);
+  const double m2 = double(mr) * double(mr) + double(mi) * double(mi);
+  if (!grad_logw<N>(G, i, K, m2, g == 0)) {
+    if (g == 0) G.pbuf[(GradRaw<N>::words - 1) * G.count + i] = 0.0;  // nothing for the second kernel
+    return;
+  }
+  // The forward values go through LDS (each lane its own slots, [slot][lane]): reloaded
+  // there, they start the reverse sweep as fresh values, so the compiler does not keep the
+  // forward pass's intermediates live across the sweep.
+  {
+    __shared__ float stage[GradStage<N>::slots * 256];
+    volatile float* st = stage + threadIdx.x;
+    int o = 0;
+    static_for<0, SP::count>([&](auto sc) {
+      constexpr int q = decltype(sc)::value;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        st[256 * o++] = J[q].re[c];
+        st[256 * o++] = J[q].im[c];
+      }
+      if constexpr (q >= L) {
+        st[256 * o++] = Sr[q];
+        st[256 * o++] = Si[q];
+      }
+    });
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      st[256 * o++] = V.re[c];
+      st[256 * o++] = V.im[c];
+    }
+    o = 0;
+    static_for<0, SP::count>([&](auto sc) {
+      constexpr int q = decltype(sc)::value;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        J[q].re[c] = st[256 * o++];
+        J[q].im[c] = st[256 * o++];
+      }
+      if constexpr (q >= L) {
+        Sr[q] = st[256 * o++];
+        Si[q] = st[256 * o++];
+      }
+    });
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      V.re[c] = st[256 * o++];
+      V.im[c] = st[256 * o++];
+    }
+  }
+  cvl<T, C> srcb[L], e0b;
+  T kb[L][C];
+  bg_reverse_g<L, GL, T>(ls, ks, J, Sr, Si, e0, V, T(2.0 * double(mr) / m2), T(2.0 * double(mi) / m2), srcb, e0b,
+                         kb);
+  // this lane's components of the raw adjoints (contravariant momentum adjoints)
+  double* o = G.pbuf + i;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int mu = 2 * g + c;
+      o[GradRaw<N>::at(t, mu) * G.count] = double(ls.sg[c] * kb[t - 1][c]);
+      o[GradRaw<N>::at(t, 4 + mu) * G.count] = double(srcb[t - 1].re[c]);
+      o[GradRaw<N>::at(t, 8 + mu) * G.count] = double(srcb[t - 1].im[c]);
+    }
+  }
+  if (g == 0) o[(GradRaw<N>::words - 1) * G.count] = 1.0;
+}
+
+// Second gradient kernel (one lane per event): from the recursion's adjoints that k_grad or
+// k_grad_g left in pbuf, the helicity sources' and momenta's adjoints (CM frame), RAMBO's
+// conformal map, q(rho) and x1, x2.  Events with |A|^2 = 0 were completed by the first.
+template <int N>
+__global__ __launch_bounds__(256) void k_grad_back(GradArgs G) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.count) return;
+  const double* o = G.pbuf + i;
+  if (o[(GradRaw<N>::words - 1) * G.count] == 0.0) return;
+  GradKin<N> K;
+  grad_front<N>(G, i, K);
+  double pb[N][4];
+  double rsb = 0.0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) pb[0][mu] = 0.0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double sg = K.leg[t] < 2u ? -K.sc : K.sc;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) pb[t][mu] = sg * o[GradRaw<N>::at(t, mu) * G.count];
+    if (K.leg[t] >= 2u) {
+      cv4<double> eb;
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        eb.re[mu] = o[GradRaw<N>::at(t, 4 + mu) * G.count];
+        eb.im[mu] = o[GradRaw<N>::at(t, 8 + mu) * G.count];
+      }
+      polarisation_adj<double>(K.pc[t], (K.hel >> K.leg[t]) & 1u, eb, pb[t]);
+    } else {
+      rsb += 0.5 * (pb[t][0] - pb[t][3]);  // leg 1: p = (rs/2)(1, 0, 0, -1)
+    }
+  }
+  grad_back<N>(G, i, K, pb, rsb);
 }
 
 }  // namespace bgk

@@ -532,8 +532,17 @@ int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const 
   G.grad_x = grad_x;
   G.logw = logw;
   G.log_const = log_weight_const(cfg->n, cfg->alpha_s);
+  hipStream_t s = (hipStream_t)stream;
+  Workspace ws{nullptr, s};
+  // the recursion's adjoints between the two gradient kernels: 12 (n - 1) + 1 words per event
+  if (hipMallocAsync((void**)&ws.p, (size_t)N * (12 * (cfg->n - 1) + 1) * sizeof(double), s) != hipSuccess) {
+    (void)hipGetLastError();
+    ws.p = nullptr;
+    return BG_ENOMEM;
+  }
+  G.pbuf = ws.p;
   const Shape sh = shape_of(cfg->n, cfg->prec);
-  return from_hip(L->grad(G, sh.block, (hipStream_t)stream));
+  return from_hip(L->grad(G, sh.block, s));
 }
 
 }  // extern "C"

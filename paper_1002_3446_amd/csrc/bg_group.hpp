@@ -212,15 +212,15 @@ __device__ __forceinline__ void span_vertex_g(const LaneShare<G, T>& ls, const K
   }
 }
 
-// Forward recursion and closure m = eps0 . V[0..L-1] (every lane of the group gets m).
+// Forward recursion: every stored current and span scalar, and the undivided bracket sum V
+// of the full span (this lane's components).
 template <int L, int G, typename T, typename KS>
-__device__ __forceinline__ void bg_amplitude_g(const LaneShare<G, T>& ls, const KS& ks,
-                                               const cvl<T, 4 / G> (&src)[L], const cvl<T, 4 / G>& eps0,
-                                               double& m_re, double& m_im) {
+__device__ __forceinline__ void bg_forward_g(const LaneShare<G, T>& ls, const KS& ks,
+                                             const cvl<T, 4 / G> (&src)[L], cvl<T, 4 / G> (&J)[Spans<L>::count],
+                                             T (&Sr)[Spans<L>::count], T (&Si)[Spans<L>::count],
+                                             cvl<T, 4 / G>& Vfull) {
   constexpr int C = 4 / G;
   using SP = Spans<L>;
-  cvl<T, C> J[SP::count];
-  T Sr[SP::count], Si[SP::count];
   static_for<0, L>([&](auto ac) { J[decltype(ac)::value] = src[decltype(ac)::value]; });
   static_for<2, L>([&](auto lc) {
     constexpr int len = decltype(lc)::value;
@@ -239,9 +239,21 @@ __device__ __forceinline__ void bg_amplitude_g(const LaneShare<G, T>& ls, const 
       Si[s] = si;
     });
   });
-  cvl<T, C> V;
   T sr, si;
-  span_vertex_g<L, 0, L - 1, G, T>(ls, ks, J, Sr, Si, V, sr, si);
+  span_vertex_g<L, 0, L - 1, G, T>(ls, ks, J, Sr, Si, Vfull, sr, si);
+}
+
+// Forward recursion and closure m = eps0 . V[0..L-1] (every lane of the group gets m).
+template <int L, int G, typename T, typename KS>
+__device__ __forceinline__ void bg_amplitude_g(const LaneShare<G, T>& ls, const KS& ks,
+                                               const cvl<T, 4 / G> (&src)[L], const cvl<T, 4 / G>& eps0,
+                                               double& m_re, double& m_im) {
+  constexpr int C = 4 / G;
+  using SP = Spans<L>;
+  cvl<T, C> J[SP::count];
+  T Sr[SP::count], Si[SP::count];
+  cvl<T, C> V;
+  bg_forward_g<L, G, T>(ls, ks, src, J, Sr, Si, V);
   T mr, mi;
   cdot_g<G>(ls, eps0, V, mr, mi);
   m_re = double(mr);

@@ -65,9 +65,24 @@ hipError_t BG_NAME(launch_amp2_2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const
 }
 #endif
 #elif BG_KIND == 2
+// Two kernels: the recursion and its reverse sweep (one or two lanes per event), then the
+// helicity-source, momentum, RAMBO and x adjoints (one lane per event).
+#if BG_PREC == 32 && BG_N >= 6 && BG_N <= 8
+#define BG_GRAD_PAIRS 1
+#else
+#define BG_GRAD_PAIRS 0
+#endif
+static_assert(grad_lane_pairs(BG_N, BG_PREC) == (BG_GRAD_PAIRS == 1), "gradient lane-pair condition");
 hipError_t BG_NAME(launch_grad_n, BG_N, BG_PREC, BG_KIND)(const GradArgs& G, int block, hipStream_t s) {
+#if BG_GRAD_PAIRS
+  (void)block;
+  const int64_t nb = (2 * G.count + 255) / 256;  // 256 lanes: the LDS staging fills a CU
+  hipLaunchKernelGGL((k_grad_g<BG_N, Real>), dim3((unsigned)nb), dim3(256), 0, s, G);
+#else
   const int64_t nb = (G.count + block - 1) / block;
   hipLaunchKernelGGL((k_grad<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, G);
+#endif
+  hipLaunchKernelGGL((k_grad_back<BG_N>), dim3((unsigned)((G.count + 255) / 256)), dim3(256), 0, s, G);
   return hipGetLastError();
 }
 #endif

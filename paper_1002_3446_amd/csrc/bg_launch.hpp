@@ -21,6 +21,10 @@ constexpr bool lds_span_table(int n, int prec) { return prec == 32 && n <= 8; }
 constexpr bool has_lane_pairs(int n, int prec) { return prec == 32 ? n >= 9 : n >= 6; }
 constexpr int default_lanes(int n, int prec) { return prec == 32 ? (n >= 10 ? 2 : 1) : (n >= 7 ? 2 : 1); }
 
+// The gradient kernel with an event on two lanes (forward values staged in LDS, which
+// bounds it to FP32 n <= 8); elsewhere one lane per event.
+constexpr bool grad_lane_pairs(int n, int prec) { return prec == 32 && n >= 6 && n <= 8; }
+
 struct GradArgs {
   int64_t count;
   double sqrt_s;
@@ -36,6 +40,7 @@ struct GradArgs {
   double* grad_x;
   double* logw;
   double log_const;  // log of the event-independent factors of w_int
+  double* pbuf;      // workspace [12 (n - 1) + 1][count]: recursion adjoints between the two kernels
 };
 
 using GenerateFn = hipError_t (*)(const GenClass& C, double* partials, int block, hipStream_t s);
