@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--recursion", action="store_true",
                     help="with --no-extras: still time the recursion kernel (bg_amp2) alone")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="with --no-extras: still time the forward + adjoint through the torch Function")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM counters)")
     a = ap.parse_args()
@@ -292,6 +294,8 @@ def main():
 
     if a.recursion and a.no_extras:
         line["recursion_kernel"] = recursion_rate(bg, torch)
+    if a.adjoint and a.no_extras:
+        line["adjoint"] = adjoint_rate(bg, torch, steps=2)
     if not a.no_extras:
         extras = {}
         cfg64 = bg.config(n, prec=64, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)

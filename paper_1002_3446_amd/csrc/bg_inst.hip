@@ -33,9 +33,11 @@ static_assert(has_lane_pairs(BG_N, BG_PREC) == (BG_PAIRS == 1), "lane-pair build
 #if BG_KIND == 0
 hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
                                                               hipStream_t s) {
-  if (lds_span_table(BG_N, BG_PREC)) block = kLdsLanes;
+  const bool table = lds_span_table(BG_N, BG_PREC);
+  if (table) block = kLdsLanes;
   const int64_t nb = (C.count + block - 1) / block;
-  hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, C, partials);
+  hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), table ? 0 : perm_lds_bytes(BG_N, block),
+                     s, C, partials);
   return hipGetLastError();
 }
 #if BG_PAIRS

@@ -11,10 +11,225 @@
 
 namespace bgk {
 
-// Lab-frame physical momenta of all N legs in recursion-position order (position 0 is
-// leg 0, position t >= 1 is leg nib(A, t-1)), with the per-event draws and kinematics.
+// One event's kinematics: the centre-of-mass momenta in recursion-position order (position 0
+// is leg 0, position t >= 1 is leg nib(A, t-1)) for the recursion, and the lab momenta of
+// the outgoing gluons in leg order for the cuts and outputs.
 template <int N>
 struct EventKin {
+  double pc[N][4];      // partonic centre-of-mass momenta (RAMBO frame), position order
+  double pl[N - 2][4];  // lab momenta of the outgoing legs 2..N-1, leg order
+  uint32_t leg[N];      // leg at each position
+  uint32_t hel;
+  double x1, x2, shat;
+};
+
+// Per-lane LDS column through which the outgoing momenta go from leg order to position
+// order: slot (4 p + mu) of lane l at perm[(4 p + mu) * stride + l].  Each lane reads only
+// what it wrote, so no barrier is needed.
+struct PermLds {
+  double* col;  // &perm[0][lane]
+  int stride;
+};
+
+// The column in the kernel's dynamic LDS (launched with perm_lds_bytes(N, blockDim) bytes).
+__device__ __forceinline__ PermLds dyn_perm() {
+  extern __shared__ double perm_dyn[];
+  return PermLds{perm_dyn + threadIdx.x, (int)blockDim.x};
+}
+
+// Builds an event's phase-space point (Sec. 3: RAMBO then the longitudinal boost) from
+// Philox draws or from caller inputs; writes the optional draw outputs when store is set.
+// RAMBO runs over the outgoing legs in leg order (fixed indices, no work for the beams);
+// their CM momenta reach the recursion positions through the lane's LDS column.
+template <int N>
+__device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventKin<N>& ev, PermLds perm,
+                                            bool store = true) {
+  constexpr int NF = N - 2;
+  const uint64_t e = C.first_event + (uint64_t)i;
+  EventRng rng{(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)N, C.key0, C.key1};
+  const u32x4 b0 = rng.block(0);
+
+  // colour ordering and helicities
+  uint64_t A;
+  if (C.in_order) {
+    A = 0;
+#pragma unroll
+    for (int t = 1; t < N; ++t) {
+      // a leg index outside 1..N-1 is clamped so that malformed input never addresses
+      // outside the event's arrays
+      const uint32_t l = C.in_order[i * N + t];
+      A |= (uint64_t)(l < 1u ? 1u : (l > (uint32_t)(N - 1) ? (uint32_t)(N - 1) : l)) << (4 * (t - 1));
+    }
+  } else if (C.random_order) {
+    A = shuffle_order<N>(rng);
+  } else {
+    A = identity_order<N>();
+  }
+  ev.leg[0] = 0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) ev.leg[t] = nib(A, t - 1);
+  ev.hel = C.in_hel ? C.in_hel[i] : (b0.v[2] & ((1u << N) - 1u));
+
+  // parton fractions
+  double sqrt_shat;
+  if (C.use_pdf) {
+    if (C.in_x) {
+      ev.x1 = C.in_x[2 * i];
+      ev.x2 = C.in_x[2 * i + 1];
+    } else {
+      ev.x1 = pdf_sample(u01(b0.v[0]), C.pdf);
+      ev.x2 = pdf_sample(u01(b0.v[1]), C.pdf);
+    }
+    ev.shat = ev.x1 * ev.x2 * C.sqrt_s * C.sqrt_s;
+    sqrt_shat = sqrt(ev.shat);
+  } else {
+    ev.x1 = ev.x2 = 1.0;
+    ev.shat = C.sqrt_s * C.sqrt_s;
+    sqrt_shat = C.sqrt_s;
+  }
+
+  // RAMBO over the outgoing legs: raw q, then the conformal map
+  double q[NF][4];
+  double Q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < NF; ++p) {
+    double r[4];
+    if (C.in_u) {
+      const double* u = C.in_u + (i * NF + p) * 4;
+      r[0] = u[0]; r[1] = u[1]; r[2] = u[2]; r[3] = u[3];
+    } else {
+      const u32x4 w = rng.block(1u + (uint32_t)p);
+      r[0] = u01(w.v[0]); r[1] = u01(w.v[1]); r[2] = u01(w.v[2]); r[3] = u01(w.v[3]);
+    }
+    rambo_q(r[0], r[1], r[2], r[3], q[p]);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) perm.col[(4 * p + mu) * perm.stride] = q[p][mu];
+    if (store && C.out.uniforms) {
+      double* uo = C.out.uniforms + (i * NF + p) * 4;
+      uo[0] = r[0]; uo[1] = r[1]; uo[2] = r[2]; uo[3] = r[3];
+    }
+  }
+  // Q summed in position order (as the position-order form does, so that every launch form
+  // gives bitwise the same momenta)
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const uint32_t j = ev.leg[t];
+    const int slot = 4 * (int)(j >= 2u ? j - 2u : 0u);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) Q[mu] += j >= 2u ? perm.col[(slot + mu) * perm.stride] : 0.0;
+  }
+  RamboMap map;
+  map.init(Q, sqrt_shat);
+  const double rr = 2.0 * sqrt(ev.x1 * ev.x2);
+  const double ch = (ev.x1 + ev.x2) / rr, sh = (ev.x1 - ev.x2) / rr;
+#pragma unroll
+  for (int p = 0; p < NF; ++p) {
+    double pc[4];
+    map.apply(q[p], pc);
+    ev.pl[p][0] = pc[0] * ch + pc[3] * sh;
+    ev.pl[p][1] = pc[1];
+    ev.pl[p][2] = pc[2];
+    ev.pl[p][3] = pc[3] * ch + pc[0] * sh;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) perm.col[(4 * p + mu) * perm.stride] = pc[mu];
+  }
+  // positions: beams directly, outgoing legs from the lane's LDS column
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    const uint32_t j = ev.leg[t];
+    const int slot = 4 * (int)(j >= 2u ? j - 2u : 0u);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) ev.pc[t][mu] = perm.col[(slot + mu) * perm.stride];
+    if (j < 2u) {
+      ev.pc[t][0] = 0.5 * sqrt_shat; ev.pc[t][1] = 0.0; ev.pc[t][2] = 0.0;
+      ev.pc[t][3] = j == 0u ? 0.5 * sqrt_shat : -0.5 * sqrt_shat;
+    }
+  }
+  if (!store) return;
+  if (C.out.hel) C.out.hel[i] = ev.hel;
+  if (C.out.order) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) C.out.order[i * N + t] = (uint8_t)ev.leg[t];
+  }
+  if (C.out.x12) {
+    C.out.x12[2 * i] = ev.x1;
+    C.out.x12[2 * i + 1] = ev.x2;
+  }
+  if (C.out.momenta) {
+    double* mo = C.out.momenta + i * N * 4;
+    const double e1 = 0.5 * C.sqrt_s * ev.x1, e2 = 0.5 * C.sqrt_s * ev.x2;
+    mo[0] = e1; mo[1] = 0.0; mo[2] = 0.0; mo[3] = e1;
+    mo[4] = e2; mo[5] = 0.0; mo[6] = 0.0; mo[7] = -e2;
+#pragma unroll
+    for (int p = 0; p < NF; ++p) {
+      mo[8 + 4 * p] = ev.pl[p][0]; mo[9 + 4 * p] = ev.pl[p][1];
+      mo[10 + 4 * p] = ev.pl[p][2]; mo[11 + 4 * p] = ev.pl[p][3];
+    }
+  }
+}
+
+// eta = asinh(pz / pT) of a momentum with transverse momentum pT, as sign(pz) log1p(x) with
+// x = r (1 + |pz| / (|p| + pT)), r = |pz| / pT: the same function, since
+// |p| - pT = pz^2 / (|p| + pT).  log1p(x) is taken as log(u) x / (u - 1) with u = 1 + x
+// (Goldberg's construction, a few ulp), so small |eta| keeps its relative precision;
+// pT = 0 gives +-inf.
+__device__ __forceinline__ double pseudorapidity(double pt, double pz) {
+#pragma clang fp contract(off)
+  const double az = fabs(pz);
+  const double pabs = sqrt(pt * pt + az * az);
+  const double x = (az / pt) * (1.0 + az / (pabs + pt));
+  const double u = 1.0 + x;
+  const double d = u - 1.0;
+  const double e = d == 0.0 ? x : (isinf(x) ? x : log_fp64(u) * (x / d));
+  return copysign(e, pz);
+}
+
+// Jet cuts and observables (Sec. 3, Sec. 4) on the outgoing legs (lab frame).  H_T is summed
+// in position order through the lane's LDS column, as the position-order form sums it.
+template <int N>
+__device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, PermLds perm, double& ht,
+                                     double& rmin) {
+  // no fused multiply-adds: both forms of the cuts round exactly as written
+#pragma clang fp contract(off)
+  constexpr int NF = N - 2;
+  double pt[NF], eta[NF], phi[NF];
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < NF; ++p) {
+    const double* m = ev.pl[p];
+    pt[p] = sqrt(m[1] * m[1] + m[2] * m[2]);
+    eta[p] = pseudorapidity(pt[p], m[3]);
+    phi[p] = atan2(m[2], m[1]);
+    perm.col[p * perm.stride] = pt[p];
+    ok = ok && (pt[p] > C.pt_min) && (fabs(eta[p]) < C.eta_max);
+  }
+  ht = 0.0;
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const uint32_t j = ev.leg[t];
+    ht += j >= 2u ? perm.col[(int)(j >= 2u ? j - 2u : 0u) * perm.stride] : 0.0;
+  }
+  double dr2min = 1e300;
+  const double pi = 3.14159265358979323846;
+  static_for<0, NF>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    static_for<a + 1, NF>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      double dphi = fabs(phi[a] - phi[b]);
+      dphi = dphi > pi ? 2.0 * pi - dphi : dphi;
+      const double deta = eta[a] - eta[b];
+      dr2min = fmin(dr2min, deta * deta + dphi * dphi);
+    });
+  });
+  rmin = sqrt(dr2min);
+  return ok && (dr2min > C.dr_min * C.dr_min);
+}
+
+// The same kinematics in recursion-position order throughout (lab momenta of all N legs),
+// without the LDS permutation: used where one event spans several lanes, whose register
+// budget the leg-order form's extra arrays exceed.
+template <int N>
+struct EventKinPos {
   double p[N][4];   // physical lab momenta, position order
   double pc[N][4];  // partonic centre-of-mass momenta (RAMBO frame), position order
   uint32_t leg[N];  // leg at each position
@@ -22,10 +237,10 @@ struct EventKin {
   double x1, x2, shat;
 };
 
-// Builds an event's phase-space point (Sec. 3: RAMBO then the longitudinal boost) from
-// Philox draws or from caller inputs; writes the optional draw outputs when store is set.
+// (RAMBO evaluated per position: the beam positions repeat an outgoing leg's draws and are
+// overwritten.)
 template <int N>
-__device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventKin<N>& ev, bool store = true) {
+__device__ __forceinline__ void build_event_positions(const GenClass& C, int64_t i, EventKinPos<N>& ev, bool store = true) {
   constexpr int NF = N - 2;
   const uint64_t e = C.first_event + (uint64_t)i;
   EventRng rng{(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)N, C.key0, C.key1};
@@ -139,24 +354,10 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
   }
 }
 
-// eta = asinh(pz / pT) of a momentum with transverse momentum pT, as sign(pz) log1p(x) with
-// x = r (1 + |pz| / (|p| + pT)), r = |pz| / pT: the same function, since
-// |p| - pT = pz^2 / (|p| + pT).  log1p(x) is taken as log(u) x / (u - 1) with u = 1 + x
-// (Goldberg's construction, a few ulp), so small |eta| keeps its relative precision;
-// pT = 0 gives +-inf.
-__device__ __forceinline__ double pseudorapidity(double pt, double pz) {
-  const double az = fabs(pz);
-  const double pabs = sqrt(pt * pt + az * az);
-  const double x = (az / pt) * (1.0 + az / (pabs + pt));
-  const double u = 1.0 + x;
-  const double d = u - 1.0;
-  const double e = d == 0.0 ? x : (isinf(x) ? x : log_fp64(u) * (x / d));
-  return copysign(e, pz);
-}
-
-// Jet cuts and observables (Sec. 3, Sec. 4) on the outgoing legs.
+// cuts() on position-ordered lab momenta (the beam positions masked).
 template <int N>
-__device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, double& ht, double& rmin) {
+__device__ __forceinline__ bool cuts_positions(const GenClass& C, const EventKinPos<N>& ev, double& ht, double& rmin) {
+#pragma clang fp contract(off)
   double pt[N], eta[N], phi[N];
   bool ok = true;
   ht = 0.0;
@@ -225,6 +426,10 @@ __device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const ui
   const cv4<T> e0 = polarisation<T>(p[0], (hel >> leg[0]) & 1u);
   double mr, mi;
   if constexpr (LDS) {
+    // the generation kernel carries its momentum permutation (doubles) in this memory: the
+    // barrier keeps the compiler from moving the table fill above those accesses (the
+    // workgroup is one wave, so it costs nothing else)
+    __syncthreads();
     SpanKLds<N - 1, kLdsLanes> ks{tab->k + threadIdx.x, tab->p + threadIdx.x};
     ks.fill(k);
     bg_amplitude<N - 1, T>(ks, src, e0, mr, mi);
@@ -307,11 +512,20 @@ __device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst)
 // values), the recursion is shared, and lane g = 0 writes the outputs and returns w
 // (the others return 0).
 template <int N, typename T, bool LDS = false, int G = 1>
-__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, LdsTable<N>* tab = nullptr, int g = 0) {
-  EventKin<N> ev;
-  build_event<N>(C, i, ev, g == 0);
+__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, PermLds perm, LdsTable<N>* tab = nullptr,
+                                               int g = 0) {
+  using Kin = typename std::conditional<G == 1, EventKin<N>, EventKinPos<N>>::type;
+  Kin ev;
   double ht, rmin;
-  const bool pass = cuts<N>(C, ev, ht, rmin);
+  bool pass;
+  if constexpr (G == 1) {
+    build_event<N>(C, i, ev, perm, g == 0);
+    pass = cuts<N>(C, ev, perm, ht, rmin);
+  } else {
+    (void)perm;
+    build_event_positions<N>(C, i, ev, g == 0);
+    pass = cuts_positions<N>(C, ev, ht, rmin);
+  }
   // |A|^2 is Lorentz invariant: evaluated in the partonic centre-of-mass frame
   double a2;
   if constexpr (G == 1)
@@ -340,18 +554,23 @@ __device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, Lds
 }
 
 // Single-class generation: one event per lane, one compensated partial per workgroup.
-// Launch: one event per lane, blockDim.x = kLdsLanes where UseLdsK holds, else any of
-// {64, 128, 192, 256}; partials may be NULL.
+// Launch: one event per lane, blockDim.x = kLdsLanes where UseLdsK holds (no dynamic LDS),
+// else any of {64, 128, 192, 256} with perm_lds_bytes(N, blockDim.x) bytes of dynamic LDS;
+// partials may be NULL.
 template <int N, typename T>
 __global__ __launch_bounds__((UseLdsK<N, T>::value ? kLdsLanes : 256)) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate(
     GenClass C, double* partials) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double w = 0.0;
   if constexpr (UseLdsK<N, T>::value) {
+    // the span table's memory first carries the momentum permutation (one wave per
+    // workgroup: every lane has read its momenta before any lane fills the table)
     __shared__ LdsTable<N> tab;
-    if (i < C.count) w = generate_one<N, T, true>(C, i, &tab);
+    static_assert(sizeof(LdsTable<N>) >= sizeof(double) * 4 * (N - 2) * kLdsLanes, "permutation fits the table");
+    const PermLds perm{reinterpret_cast<double*>(&tab) + threadIdx.x, kLdsLanes};
+    if (i < C.count) w = generate_one<N, T, true>(C, i, perm, &tab);
   } else {
-    if (i < C.count) w = generate_one<N, T>(C, i);
+    if (i < C.count) w = generate_one<N, T>(C, i, dyn_perm());
   }
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
 }
@@ -390,7 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int g = (int)(threadIdx.x % G);
   double w = 0.0;
-  if (i < C.count) w = generate_one<N, T, false, G>(C, i, nullptr, g);
+  if (i < C.count) w = generate_one<N, T, false, G>(C, i, PermLds{nullptr, 0}, nullptr, g);
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
 }
 

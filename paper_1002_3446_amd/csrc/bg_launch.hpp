@@ -13,6 +13,10 @@ namespace bgk {
 // (SpanKLds) and run with 64-lane workgroups: at n = 8 four workgroups use 143 KB of a
 // compute unit's 160 KB.  Larger n and FP64 sum the FP64 leg momenta at every use.
 constexpr int kLdsLanes = 64;
+
+// Dynamic LDS of the generation kernels without the span table: the per-lane column of the
+// leg-to-position momentum permutation, 4 (n - 2) doubles per lane.
+constexpr unsigned perm_lds_bytes(int n, int block) { return 8u * 4u * (unsigned)(n - 2) * (unsigned)block; }
 constexpr bool lds_span_table(int n, int prec) { return prec == 32 && n <= 8; }
 
 // Multiplicities whose kernels are also built with an event spread over two lanes (the

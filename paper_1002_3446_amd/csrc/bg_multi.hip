@@ -20,17 +20,17 @@ using Real = float;
 namespace {
 
 template <typename T>
-__device__ __forceinline__ double generate_any(int n, const GenClass& C, int64_t e) {
+__device__ __forceinline__ double generate_any(int n, const GenClass& C, int64_t e, PermLds perm) {
   switch (n) {
-    case 4: return generate_one<4, T>(C, e);
-    case 5: return generate_one<5, T>(C, e);
-    case 6: return generate_one<6, T>(C, e);
-    case 7: return generate_one<7, T>(C, e);
-    case 8: return generate_one<8, T>(C, e);
-    case 9: return generate_one<9, T>(C, e);
-    case 10: return generate_one<10, T>(C, e);
-    case 11: return generate_one<11, T>(C, e);
-    default: return generate_one<12, T>(C, e);
+    case 4: return generate_one<4, T>(C, e, perm);
+    case 5: return generate_one<5, T>(C, e, perm);
+    case 6: return generate_one<6, T>(C, e, perm);
+    case 7: return generate_one<7, T>(C, e, perm);
+    case 8: return generate_one<8, T>(C, e, perm);
+    case 9: return generate_one<9, T>(C, e, perm);
+    case 10: return generate_one<10, T>(C, e, perm);
+    case 11: return generate_one<11, T>(C, e, perm);
+    default: return generate_one<12, T>(C, e, perm);
   }
 }
 
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const MultiClass& mc = classes[tl.cls];
     CSum w{0.0, 0.0}, w2{0.0, 0.0};
     for (int64_t i = tl.first + threadIdx.x; i < tl.first + tl.count; i += blockDim.x) {
-      const double x = generate_any<T>(mc.n, mc.C, i);
+      const double x = generate_any<T>(mc.n, mc.C, i, dyn_perm());
       w = cs_add(w, CSum{x, 0.0});
       w2 = cs_add(w2, CSum{x * x, 0.0});
     }
@@ -97,7 +97,9 @@ __global__ __launch_bounds__(256) void k_finalize_multi(const MultiClass* __rest
 
 hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
                                   int* counter, double* partials, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((k_generate_multi<Real>), dim3(grid), dim3(block), 0, s, classes, tiles, ntiles, counter,
+  // dynamic LDS: the momentum permutation column of the largest multiplicity
+  hipLaunchKernelGGL((k_generate_multi<Real>), dim3(grid), dim3(block), perm_lds_bytes(12, block), s, classes, tiles,
+                     ntiles, counter,
                      partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
