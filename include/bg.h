@@ -140,7 +140,8 @@ int bg_set_launch(int n, int prec, int block, int tile_iters);
 int bg_get_launch(int n, int prec, int *block, int *tile_iters);
 
 /* Lanes of a wave that share one event in the single-class kernels of (n, prec) (bg_generate
- * and bg_amp2; the persistent multi-class kernel and bg_amp2_grad use one lane per event):
+ * and bg_amp2; the persistent multi-class kernel uses one lane per event, and bg_amp2_grad
+ * uses two for the recursion adjoint of FP32 n = 6..8 and one otherwise, independent of this):
  * 1, or 2 where the library holds the two-lane form (FP32 n >= 9, FP64 n >= 6; else
  * BG_ENOTSUP); 0 restores the default (2 for FP32 n >= 10 and FP64 n >= 7, else 1).  With
  * two lanes each holds two of the four Lorentz components of every current: half the
