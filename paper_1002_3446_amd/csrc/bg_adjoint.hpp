@@ -312,7 +312,7 @@ __device__ __forceinline__ void rambo_q_adj(double r1, double r2, double r3, dou
   const double c = 2.0 * r1 - 1.0;
   const double st = sqrt(1.0 - c * c);
   double sp, cp;
-  sincospi(2.0 * r2, &sp, &cp);
+  sincospi_fp64(2.0 * r2, &sp, &cp);
   const double q0 = -log_fp64(r3 * r4);
   const double q0b = qb[0] + qb[1] * st * cp + qb[2] * st * sp + qb[3] * c;
   const double stb = q0 * (qb[1] * cp + qb[2] * sp);

@@ -281,7 +281,7 @@ __device__ __forceinline__ void rambo_q(double r1, double r2, double r3, double 
   const double c = 2.0 * r1 - 1.0;
   const double st = sqrt(1.0 - c * c);
   double sp, cp;
-  sincospi(2.0 * r2, &sp, &cp);
+  sincospi_fp64(2.0 * r2, &sp, &cp);
   const double q0 = -log_fp64(r3 * r4);
   q[0] = q0;
   q[1] = q0 * st * cp;
@@ -293,12 +293,13 @@ struct RamboMap {
   double bx, by, bz, gamma, a, X;
   __device__ __forceinline__ void init(const double Q[4], double sqrt_shat) {
     const double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
-    bx = -Q[1] / M;
-    by = -Q[2] / M;
-    bz = -Q[3] / M;
-    gamma = Q[0] / M;
+    const double iM = 1.0 / M;
+    bx = -Q[1] * iM;
+    by = -Q[2] * iM;
+    bz = -Q[3] * iM;
+    gamma = Q[0] * iM;
     a = 1.0 / (1.0 + gamma);
-    X = sqrt_shat / M;
+    X = sqrt_shat * iM;
   }
   __device__ __forceinline__ void apply(const double q[4], double p[4]) const {
     const double bq = bx * q[1] + by * q[2] + bz * q[3];

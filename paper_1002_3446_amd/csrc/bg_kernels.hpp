@@ -168,20 +168,16 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
   }
 }
 
-// eta = asinh(pz / pT) of a momentum with transverse momentum pT, as sign(pz) log1p(x) with
-// x = r (1 + |pz| / (|p| + pT)), r = |pz| / pT: the same function, since
-// |p| - pT = pz^2 / (|p| + pT).  log1p(x) is taken as log(u) x / (u - 1) with u = 1 + x
-// (Goldberg's construction, a few ulp), so small |eta| keeps its relative precision;
-// pT = 0 gives +-inf.
+// eta = asinh(pz / pT) of a momentum with transverse momentum pT, as sign(pz) log((|p| + |pz|)
+// / pT): the same function, since (|p| + |pz|)(|p| - |pz|) = pT^2.  Every step is a sum of
+// positive terms, a division or the logarithm, so the absolute error is a few units of
+// 2^-53 |eta| (the cuts and Delta R only use eta through |eta| and differences); pT = 0
+// gives +-inf.
 __device__ __forceinline__ double pseudorapidity(double pt, double pz) {
 #pragma clang fp contract(off)
   const double az = fabs(pz);
   const double pabs = sqrt(pt * pt + az * az);
-  const double x = (az / pt) * (1.0 + az / (pabs + pt));
-  const double u = 1.0 + x;
-  const double d = u - 1.0;
-  const double e = d == 0.0 ? x : (isinf(x) ? x : log_fp64(u) * (x / d));
-  return copysign(e, pz);
+  return copysign(log_fp64((pabs + az) / pt), pz);
 }
 
 // Jet cuts and observables (Sec. 3, Sec. 4) on the outgoing legs (lab frame).  H_T is summed
