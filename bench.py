@@ -104,6 +104,12 @@ def run_steps(bg, torch, cfg, N, steps, warmup, outputs):
     return wall, [a.elapsed_time(b) for a, b in evs], out
 
 
+def scaling_measure(t_n: float, t_prev: float, n: int, m: int) -> float:
+    """Polynomial scaling measure of Table 1 (Sec. 4): P_n(m) = ((n-1)/n) (T_n / T_(n-1))^(1/m)
+    for per-event times T; it approaches 1 when T grows like n^m."""
+    return (n - 1) / n * (t_n / t_prev) ** (1.0 / m)
+
+
 def mixed_rate(bg, torch):
     """n = 4..12 with 2^(26-n) events each (8,372,224 events), FP32: one persistent launch,
     one class after another, and classes on concurrent streams; the rate is the fastest."""
@@ -139,7 +145,10 @@ def mixed_rate(bg, torch):
     return {"mixed_n4_12_fp32_events_per_s": total / (min(ms_modes.values()) * 1e-3),
             "mixed_n4_12_ms_by_mode": ms_modes, "mixed_n4_12_tuned_mode": mode,
             "mixed_n4_12_sum_of_single_ms": sum(per_n.values()),
-            "single_class_fp32_events_per_s": {str(n): counts[i] / (per_n[n] * 1e-3) for i, n in enumerate(ns)}}
+            "single_class_fp32_events_per_s": {str(n): counts[i] / (per_n[n] * 1e-3) for i, n in enumerate(ns)},
+            # the paper's GPU scaling measure P_n(3) (Table 1) for these per-event times
+            "single_class_fp32_scaling_P3": {str(n): scaling_measure(per_n[n] / counts[i], per_n[n - 1] / counts[i - 1], n, 3)
+                                             for i, n in enumerate(ns) if i > 0}}
 
 
 def adjoint_rate(bg, torch, N=1 << 20, steps=5):
