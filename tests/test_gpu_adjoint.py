@@ -56,6 +56,27 @@ def test_grad_vs_oracle(gpu_lib, n, prec):
         assert np.median(xerr) < 1e-5 and np.median(lerr) < 1e-5
 
 
+def test_grad_full_size_sampled(gpu_lib):
+    """The adjoint workload as timed (n = 8, FP32, 2^20 events, plus a ragged tail of 37):
+    the oracle's gradient on sampled events, including the first and last."""
+    n, N = 8, (1 << 20) + 37
+    u, x, hel, order = setup(n, N, 23)
+    print(f"grad full size n={n} N={N}", flush=True)
+    gu, gx, lw = gpu_lib.amp2_grad(gpu_lib.config(n, prec=32), *dev(u, x, hel, order))
+    torch.cuda.synchronize()
+    gu, gx, lw = gu.cpu().numpy(), gx.cpu().numpy(), lw.cpu().numpy()
+    assert np.all(np.isfinite(gu)) and np.all(np.isfinite(gx))
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, 1, N - 2, N - 1], rng.integers(0, N, 300)]))
+    olw, ogu, ogx = event.log_weight_grad(event.config(n=n, use_pdf=1), u[idx], x[idx], hel[idx], order[idx])
+    err = np.abs(gu[idx] - ogu).max(1) / np.abs(ogu).max(1)
+    q = np.quantile(err, [0.5, 0.9])
+    print(f"sampled grad_u rel err p50/p90 {q}")
+    assert q[0] < 1e-4 and q[1] < 1e-2
+    assert np.median(np.abs(gx[idx] - ogx) / np.abs(ogx)) < 1e-5
+    assert np.median(np.abs(lw[idx] - olw)) < 1e-5
+
+
 def test_grad_closed_form_and_sum_rules(gpu_lib):
     n, N = 8, 2048
     u, x, hel, order = setup(n, N, 7)
