@@ -317,6 +317,64 @@ def test_full_size_sampled(gpu_lib):
     assert np.median(rel) <= 1e-4
 
 
+def test_n12_full_size_fp32_vs_fp64(gpu_lib):
+    """gg -> 10g, 2^22 events, FP32 and FP64 recursion on the same seeded events: identical
+    draws, kinematics and cuts; the FP32 error against the FP64 run per event; sampled events
+    of both against the oracle; compensated totals against the exact sums."""
+    n, N, seed = 12, 1 << 22, 0xB6000002
+    outs = ("weight", "amp2", "pass", "x12", "hel", "order", "acc")
+    r = {}
+    for prec in (32, 64):
+        print(f"generate n=12 fp{prec} N=2^22", flush=True)
+        r[prec] = to_np(gpu_lib.generate(cfg_c1(gpu_lib, n=n, prec=prec, seed=seed), N, outputs=outs))
+    for k in ("pass", "x12", "hel", "order"):
+        assert np.array_equal(r[32][k], r[64][k]), k
+    for prec in (32, 64):
+        w, acc = r[prec]["weight"], r[prec]["acc"]
+        assert abs(acc[0] + acc[1] - math.fsum(w.tolist())) <= 2 * EPS * np.abs(w).sum()
+    a32, a64 = r[32]["amp2"].astype(np.float64), r[64]["amp2"]
+    live = a64 > 0
+    q = np.quantile(np.abs(a32[live] - a64[live]) / a64[live], [0.5, 0.9, 0.99])
+    print("n=12 fp32 vs fp64 rel err p50/p90/p99", q)
+    assert q[0] <= 1e-4
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([[0, 1, N - 2, N - 1], rng.integers(0, N, 300)]))
+    oc = oracle_cfg(cfg_c1(gpu_lib, n=n, prec=64, seed=seed))
+    o = event.generate(oc, idx)
+    assert np.array_equal(r[64]["hel"][idx], o["hel"].astype(np.int64))
+    assert np.array_equal(r[64]["order"][idx], o["order"])
+    assert np.all(np.abs(r[64]["x12"][idx] - o["x12"]) <= 1e-14 * o["x12"] + x_bound(oc, o["x12"]))
+    rel32 = fp32_errors(r[32]["amp2"][idx], o["mom_cm"], o["hel"], o["order"])
+    rel64 = fp32_errors(r[64]["amp2"][idx], o["mom_cm"], o["hel"], o["order"])
+    print("n=12 sampled vs oracle: fp32 median", np.median(rel32), "fp64 median/p90", np.quantile(rel64, [0.5, 0.9]))
+    assert np.median(rel32) <= 1e-4
+    # FP64 against the long-double value; the x1, x2 conditioning widens single events only
+    assert np.median(rel64) <= 1e-12 and np.quantile(rel64, 0.9) <= 1e-10
+
+
+def test_mixed_full_size_sampled(gpu_lib):
+    """The mixed workload as timed: n = 4..12 with 2^(26-n) events each in one call with the
+    tuned strategy; per class, sampled events against the oracle and the compensated total
+    against the exact sum of the weights."""
+    ns = list(range(4, 13))
+    cfgs = [cfg_c1(gpu_lib, n=n, prec=32, seed=0xB6000003 + n) for n in ns]
+    counts = [1 << (26 - n) for n in ns]
+    print("mixed n=4..12 at 2^(26-n) events", flush=True)
+    res = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=("weight", "amp2", "pass", "x12", "acc"))]
+    rng = np.random.default_rng(2)
+    for c, N, m in zip(cfgs, counts, res):
+        w = m["weight"]
+        assert abs(m["acc"][0] + m["acc"][1] - math.fsum(w.tolist())) <= 2 * EPS * np.abs(w).sum(), c.n
+        idx = np.unique(np.concatenate([[0, N - 1], rng.integers(0, N, 60)]))
+        oc = oracle_cfg(c)
+        o = event.generate(oc, idx)
+        assert np.all(np.abs(m["x12"][idx] - o["x12"]) <= 1e-14 * o["x12"] + x_bound(oc, o["x12"])), c.n
+        flip = m["pass"][idx].astype(bool) != o["pass_"]
+        assert np.all(o["margin"][flip] < 1e-9), c.n
+        rel = fp32_errors(m["amp2"][idx], o["mom_cm"], o["hel"], o["order"])
+        assert np.median(rel) <= 1e-4, (c.n, np.median(rel))
+
+
 def test_mixed_all_multiplicities(gpu_lib, mixed_mode):
     """n = 4..12 in one persistent launch (event counts 2^(18-n)): draws, kinematics and cuts
     equal the single-class kernels', |A|^2 and weights to FP32 rounding."""
