@@ -24,8 +24,10 @@
  *     incoming partons along +z and -z; legs 2..n-1 the outgoing gluons.
  *   - A helicity word has bit i set when leg i has all-outgoing helicity +.
  *   - A colour ordering is n bytes: order[0] is the closing leg (always 0 for
- *     generated events), order[1..n-1] the ordered recursion legs.  Per-event array
- *     contents (that order is a permutation, that momenta conserve) are not checked.
+ *     generated events), order[1..n-1] the ordered recursion legs.  The compute entry
+ *     points do not check per-event array contents (that order is a permutation, that
+ *     momenta conserve); a malformed leg index is clamped into range, never followed
+ *     out of bounds.  bg_check_events checks orderings and helicity words on request.
  *   - |A|^2 is reported in the Parke-Taylor normalisation (Tr(T^a T^b) = delta^ab):
  *     the printed brackets of Eq. 3.2 carry coefficient 1, so |m|^2 = 2^(n-2) |A|^2.
  */
@@ -130,6 +132,16 @@ int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
 int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const double *x12,
                  const uint32_t *hel, const uint8_t *order, const double *gout,
                  double *grad_u, double *grad_x, double *logw, void *stream);
+
+/* Validation of the per-event inputs that bg_amp2 and bg_amp2_grad take unchecked (the
+ * ordering and helicity conventions above): writes to first_bad (a device int64_t) the
+ * smallest event index whose order row [N][n] is not a permutation of 0..n-1 or whose
+ * helicity word [N] has a bit at or above n, or -1 when every event is well formed.  Three
+ * small kernels on `stream`; read first_bad after synchronising it.  N = 0 writes -1 (hel,
+ * order may then be NULL).  Errors: BG_ENOTSUP (n outside 4..12), BG_EINVAL (N < 0 or
+ * N > (2^31 - 1) * 256, NULL first_bad, NULL hel/order with N > 0). */
+int bg_check_events(int n, int64_t N, const uint32_t *hel, const uint8_t *order, int64_t *first_bad,
+                    void *stream);
 
 /* Launch shape for one (n, prec) class: threads per workgroup (64, 128, 192 or 256) and
  * events per lane in one tile of the persistent multi-class launch (1..64; a tile holds

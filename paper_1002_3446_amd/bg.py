@@ -49,6 +49,7 @@ _lib.bg_generate.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int, _i64p, ctyp
                              ctypes.POINTER(BgOutputs), ctypes.c_void_p]
 _lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 5
 _lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 9
+_lib.bg_check_events.argtypes = [ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 4
 _lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
 _lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.bg_set_lanes.argtypes = [ctypes.c_int] * 3
@@ -166,9 +167,34 @@ def generate(cfgs, counts, inputs=None, outputs=("weight", "amp2", "obs", "pass"
     return results[0] if single else results
 
 
+# BG_DEBUG=1 in the environment: amp2 and amp2_grad validate their orderings and helicity
+# words with bg_check_events first (one device synchronisation per call)
+DEBUG_CHECKS = os.environ.get("BG_DEBUG", "") not in ("", "0")
+
+
+def check_events(n: int, hel, order) -> int:
+    """Index of the first event whose order row is not a permutation of 0..n-1 or whose
+    helicity word has a bit at or above n; -1 when all are well formed.  Synchronises the
+    current stream to read the result."""
+    N = order.shape[0]
+    res = torch.empty(1, dtype=torch.int64, device=order.device)
+    st = _lib.bg_check_events(n, N, _ptr(hel, torch.int32, (N,), "hel"), _ptr(order, torch.uint8, (N, n), "order"),
+                              _ptr(res, torch.int64, (1,), "first_bad"), _stream(order.device))
+    _check("bg_check_events", st)
+    return int(res.item())
+
+
+def _debug_check(fn: str, n: int, hel, order):
+    bad = check_events(n, hel, order)
+    if bad >= 0:
+        raise ValueError(f"{fn}: event {bad} has a malformed ordering or helicity word")
+
+
 def amp2(n: int, prec: int, mom, hel, order, out=None):
     """|A(sigma;h)|^2 for momenta [N, n, 4] float64, hel [N] int32 words, order [N, n] uint8."""
     N = mom.shape[0]
+    if DEBUG_CHECKS and N > 0:
+        _debug_check("bg_amp2", n, hel, order)
     if out is None:
         out = torch.empty(N, dtype=torch.float64, device=mom.device)
     st = _lib.bg_amp2(n, prec, N, _ptr(mom, torch.float64, (N, n, 4), "mom"), _ptr(hel, torch.int32, (N,), "hel"),
@@ -182,6 +208,8 @@ def amp2_grad(cfg: BgConfig, u, x12, hel, order, gout=None, want_logw=True):
     """(grad_u [N, 4(n-2)], grad_x [N, 2], log w_int [N]) of the log integrand weight."""
     N = u.shape[0]
     n = cfg.n
+    if DEBUG_CHECKS and N > 0:
+        _debug_check("bg_amp2_grad", n, hel, order)
     gu = torch.empty((N, 4 * (n - 2)), dtype=torch.float64, device=u.device)
     gx = torch.empty((N, 2), dtype=torch.float64, device=u.device)
     lw = torch.empty(N, dtype=torch.float64, device=u.device) if want_logw else None

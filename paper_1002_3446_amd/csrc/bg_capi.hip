@@ -320,6 +320,31 @@ int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* o
   return st;
 }
 
+
+// Input check behind bg_check_events: the smallest index of an event whose ordering is not a
+// permutation of 0..n-1 or whose helicity word has bits at or above n.
+__global__ void k_check_init(int64_t* first_bad) {
+  if (threadIdx.x == 0) first_bad[0] = INT64_MAX;
+}
+
+__global__ __launch_bounds__(256) void k_check_events(int n, int64_t count, const uint32_t* __restrict__ hel,
+                                                      const uint8_t* __restrict__ order, int64_t* first_bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  bool ok = (hel[i] >> n) == 0u;
+  uint32_t seen = 0u;
+  for (int t = 0; t < n; ++t) {
+    const uint32_t l = order[i * n + t];
+    ok = ok && l < (uint32_t)n && ((seen >> l) & 1u) == 0u;
+    seen |= 1u << (l & 31u);
+  }
+  if (!ok) atomicMin(reinterpret_cast<unsigned long long*>(first_bad), (unsigned long long)i);
+}
+
+__global__ void k_check_final(int64_t* first_bad) {
+  if (threadIdx.x == 0 && first_bad[0] == INT64_MAX) first_bad[0] = -1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -504,6 +529,17 @@ int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, 
   const Amp2Fn f = lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2;
   if (!f) return BG_ENOTSUP;
   return from_hip(f(N, mom, hel, order, amp2_out, sh.block, (hipStream_t)stream));
+}
+
+int bg_check_events(int n, int64_t N, const uint32_t* hel, const uint8_t* order, int64_t* first_bad, void* stream) {
+  if (n < 4 || n > 12) return BG_ENOTSUP;
+  if (N < 0 || N > (int64_t)0x7fffffff * 256 || !first_bad || (N > 0 && (!hel || !order))) return BG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_check_init, dim3(1), dim3(64), 0, s, first_bad);
+  if (N > 0)
+    hipLaunchKernelGGL(k_check_events, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, n, N, hel, order, first_bad);
+  hipLaunchKernelGGL(k_check_final, dim3(1), dim3(64), 0, s, first_bad);
+  return from_hip(hipGetLastError());
 }
 
 int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const double* x12, const uint32_t* hel,

@@ -58,6 +58,10 @@ def test_host_error_paths():
     assert lib.bg_amp2(8, 64, -1, None, None, None, None, None) == bg.BG_EINVAL
     assert lib.bg_amp2(8, 64, 0, None, None, None, None, None) == bg.BG_OK
     assert lib.bg_amp2(8, 64, 4, None, None, None, None, None) == bg.BG_EINVAL
+    assert lib.bg_check_events(3, 5, None, None, None, None) == bg.BG_ENOTSUP
+    assert lib.bg_check_events(8, -1, None, None, None, None) == bg.BG_EINVAL
+    assert lib.bg_check_events(8, 5, None, None, None, None) == bg.BG_EINVAL
+    assert lib.bg_check_events(8, 1 << 40, 16, 16, 16, None) == bg.BG_EINVAL
     assert lib.bg_amp2_grad(None, 4, *([None] * 9)) == bg.BG_EINVAL
     assert lib.bg_set_launch(8, 32, 96, 1) == bg.BG_EINVAL
     assert lib.bg_set_launch(8, 32, 128, 0) == bg.BG_EINVAL

@@ -88,3 +88,37 @@ def test_amp2_unsupported(gpu_lib):
         gpu_lib.amp2(n, 64, z, torch.zeros(4, dtype=torch.int32, device="cuda"),
                      torch.zeros((4, n), dtype=torch.uint8, device="cuda"))
     assert e.value.status == gpu_lib.BG_ENOTSUP
+
+
+def test_check_events(gpu_lib):
+    """bg_check_events: well-formed inputs give -1; planted malformed rows (a repeated leg, a
+    leg index n, a helicity bit n) give the smallest planted index; the binding's debug mode
+    rejects a malformed call before any amplitude is computed."""
+    n, N = 8, 5000 + 13
+    hel = inputs.helicity_words(3, N, n)
+    order = inputs.orderings(3, N, n)
+    dev = lambda h, o: (torch.tensor(h.astype(np.int64), device="cuda").to(torch.int32), torch.tensor(o, device="cuda"))
+    assert gpu_lib.check_events(n, *dev(hel, order)) == -1
+    o2, h2 = order.copy(), hel.copy()
+    o2[4000, 3] = o2[4000, 5]        # a repeated leg
+    o2[4500, 7] = n                  # a leg index out of range
+    h2[4200] |= np.uint32(1 << n)    # a helicity bit beyond the last leg
+    assert gpu_lib.check_events(n, *dev(h2, o2)) == 4000
+    h3 = hel.copy()
+    h3[N - 1] |= np.uint32(1 << 31)
+    assert gpu_lib.check_events(n, *dev(h3, order)) == N - 1
+    o4 = order.copy()
+    o4[17, 0] = 3                    # leg 3 twice, leg 0 missing
+    assert gpu_lib.check_events(n, *dev(hel, o4)) == 17
+    assert gpu_lib.check_events(n, torch.empty(0, dtype=torch.int32, device="cuda"),
+                                torch.empty((0, n), dtype=torch.uint8, device="cuda")) == -1
+    mom, _, _ = make_points(n, N, 3)
+    old = gpu_lib.DEBUG_CHECKS
+    gpu_lib.DEBUG_CHECKS = True
+    try:
+        with pytest.raises(ValueError, match="event 4000"):
+            gpu_lib.amp2(n, 32, torch.tensor(mom, device="cuda"), *dev(h2, o2))
+        good = gpu_lib.amp2(n, 32, torch.tensor(mom, device="cuda"), *dev(hel, order))
+        assert good.numel() == N
+    finally:
+        gpu_lib.DEBUG_CHECKS = old
