@@ -4,6 +4,12 @@
 #include "bg_adjoint.hpp"
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
+#if BG_KIND == 0 && BG_PREC == 32 && BG_N == 8
+#include "bg_split.hpp"
+#define BG_SPLIT 1
+#else
+#define BG_SPLIT 0
+#endif
 
 #if !defined(BG_N) || !defined(BG_PREC) || !defined(BG_KIND)
 #error "BG_N, BG_PREC and BG_KIND must be defined"
@@ -35,6 +41,11 @@ hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C,
                                                               hipStream_t s) {
   const bool table = lds_span_table(BG_N, BG_PREC);
   if (table) block = kLdsLanes;
+#if BG_SPLIT
+  // kinematics and recursion as two kernels; the fused kernel if no staging memory
+  const hipError_t e = launch_generate_split<BG_N, Real>(C, partials, s);
+  if (e != hipErrorOutOfMemory) return e;
+#endif
   const int64_t nb = (C.count + block - 1) / block;
   hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), table ? 0 : perm_lds_bytes(BG_N, block),
                      s, C, partials);
