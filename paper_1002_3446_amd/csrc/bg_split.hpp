@@ -15,13 +15,16 @@
 
 namespace bgk {
 
-// Staging layout: word w of event j of a chunk at buf[w * cap + j] (cap = chunk capacity,
-// a multiple of 64): 4N momenta (position t, component mu at 4 t + mu), s_hat, x1, x2, the
-// helicity word with the cut flag at bit 32, and the leg positions (4 bits each).
+// Staging layout: events in tiles of 64 (one wave), each tile holding its words one after
+// another, word w of event j at buf[((j / 64) * kWords + w) * 64 + j % 64], so that a wave
+// reads one contiguous block.  Words: 4N momenta (position t, component mu at 4 t + mu),
+// s_hat, x1, x2, the helicity word with the cut flag at bit 32, and the leg positions
+// (4 bits each).
 template <int N>
 struct SplitLayout {
   static constexpr int kMom = 0, kShat = 4 * N, kX1 = 4 * N + 1, kX2 = 4 * N + 2, kMeta = 4 * N + 3,
                        kLegs = 4 * N + 4, kWords = 4 * N + 5;
+  __device__ static int64_t at(int64_t j, int w) { return ((j >> 6) * kWords + w) * 64 + (j & 63); }
 };
 
 // Launch: blockDim.x in {64, 128, 256}, perm_lds_bytes(N, blockDim.x) bytes of dynamic LDS,
@@ -46,15 +49,15 @@ __global__ __launch_bounds__(256) void k_kin(GenClass C, int64_t first, int64_t 
 #pragma unroll
   for (int t = 0; t < N; ++t)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) buf[(int64_t)(L::kMom + 4 * t + mu) * cap + j] = ev.pc[t][mu];
-  buf[(int64_t)L::kShat * cap + j] = ev.shat;
-  buf[(int64_t)L::kX1 * cap + j] = ev.x1;
-  buf[(int64_t)L::kX2 * cap + j] = ev.x2;
+    for (int mu = 0; mu < 4; ++mu) buf[L::at(j, L::kMom + 4 * t + mu)] = ev.pc[t][mu];
+  buf[L::at(j, L::kShat)] = ev.shat;
+  buf[L::at(j, L::kX1)] = ev.x1;
+  buf[L::at(j, L::kX2)] = ev.x2;
   uint64_t legs = 0;
 #pragma unroll
   for (int t = 0; t < N; ++t) legs |= (uint64_t)(ev.leg[t] & 15u) << (4 * t);
-  buf[(int64_t)L::kMeta * cap + j] = __longlong_as_double((long long)((uint64_t)ev.hel | ((uint64_t)pass << 32)));
-  buf[(int64_t)L::kLegs * cap + j] = __longlong_as_double((long long)legs);
+  buf[L::at(j, L::kMeta)] = __longlong_as_double((long long)((uint64_t)ev.hel | ((uint64_t)pass << 32)));
+  buf[L::at(j, L::kLegs)] = __longlong_as_double((long long)legs);
 }
 
 // Launch: blockDim.x = kLdsLanes, ceil(cnt / kLdsLanes) workgroups, first a multiple of
@@ -74,12 +77,12 @@ __global__ __launch_bounds__(kLdsLanes) __attribute__((amdgpu_waves_per_eu(1, 1)
 #pragma unroll
     for (int t = 0; t < N; ++t)
 #pragma unroll
-      for (int mu = 0; mu < 4; ++mu) pc[t][mu] = buf[(int64_t)(L::kMom + 4 * t + mu) * cap + j];
-    const double shat = buf[(int64_t)L::kShat * cap + j];
-    const double x1 = buf[(int64_t)L::kX1 * cap + j];
-    const double x2 = buf[(int64_t)L::kX2 * cap + j];
-    const uint64_t meta = (uint64_t)__double_as_longlong(buf[(int64_t)L::kMeta * cap + j]);
-    const uint64_t legs = (uint64_t)__double_as_longlong(buf[(int64_t)L::kLegs * cap + j]);
+      for (int mu = 0; mu < 4; ++mu) pc[t][mu] = buf[L::at(j, L::kMom + 4 * t + mu)];
+    const double shat = buf[L::at(j, L::kShat)];
+    const double x1 = buf[L::at(j, L::kX1)];
+    const double x2 = buf[L::at(j, L::kX2)];
+    const uint64_t meta = (uint64_t)__double_as_longlong(buf[L::at(j, L::kMeta)]);
+    const uint64_t legs = (uint64_t)__double_as_longlong(buf[L::at(j, L::kLegs)]);
 #pragma unroll
     for (int t = 0; t < N; ++t) leg[t] = (uint32_t)(legs >> (4 * t)) & 15u;
     const uint32_t hel = (uint32_t)meta;
