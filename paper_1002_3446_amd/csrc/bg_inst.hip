@@ -42,9 +42,12 @@ hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C,
   const bool table = lds_span_table(BG_N, BG_PREC);
   if (table) block = kLdsLanes;
 #if BG_SPLIT
-  // kinematics and recursion as two kernels; the fused kernel if no staging memory
-  const hipError_t e = launch_generate_split<BG_N, Real>(C, partials, s);
-  if (e != hipErrorOutOfMemory) return e;
+  // kinematics and recursion as two kernels for large calls; the fused kernel for small
+  // ones and if there is no staging memory
+  if (C.count >= kSplitMinEvents) {
+    const hipError_t e = launch_generate_split<BG_N, Real>(C, partials, s);
+    if (e != hipErrorOutOfMemory) return e;
+  }
 #endif
   const int64_t nb = (C.count + block - 1) / block;
   hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), table ? 0 : perm_lds_bytes(BG_N, block),

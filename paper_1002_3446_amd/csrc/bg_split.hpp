@@ -108,6 +108,9 @@ __global__ __launch_bounds__(kLdsLanes) __attribute__((amdgpu_waves_per_eu(1, 1)
 // stream-ordered staging buffer; returns hipErrorOutOfMemory (nothing launched) when the
 // buffer cannot be allocated, so that the caller can run the fused kernel instead.
 constexpr int64_t kSplitChunk = int64_t(1) << 21;
+// below this many events the per-call allocation of the staging buffer costs more than the
+// split saves, and the fused kernel runs
+constexpr int64_t kSplitMinEvents = int64_t(1) << 20;
 constexpr int kKinBlock = 128;
 
 template <int N, typename T>
