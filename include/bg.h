@@ -96,10 +96,10 @@ typedef struct {
 
 /* Generate events of ncfg classes (Sec. 3).  One class: one launch of that multiplicity's
  * kernel (after a small setup launch that tabulates the inverse CDF of the parton density
- * when x1, x2 are sampled); n = 8 with FP32 recursion runs instead, per chunk of up to 2^21
- * events, a kinematics kernel and a recursion kernel joined by a stream-ordered staging
- * buffer (296 B per event of the chunk), or the single kernel if that buffer cannot be
- * allocated.  Several classes (mixed multiplicities): as chosen by
+ * when x1, x2 are sampled); n <= 8 with FP32 recursion and at least 2^20 events runs
+ * instead, per chunk of up to 2^21 events, a kinematics kernel and a recursion kernel
+ * joined by a stream-ordered staging buffer ((4n + 5) * 8 B per event of the chunk), or
+ * the single kernel if that buffer cannot be allocated.  Several classes (mixed multiplicities): as chosen by
  * bg_set_mixed_launch, either one after another, or the FP32 classes in one persistent
  * launch whose workgroups take tiles (largest n first) from a shared queue, or side by side
  * on concurrent streams.  Per-event values are reproducible for a given call and mode.

@@ -4,7 +4,7 @@
 #include "bg_adjoint.hpp"
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
-#if BG_KIND == 0 && BG_PREC == 32 && BG_N == 8
+#if BG_KIND == 0 && BG_PREC == 32 && BG_N <= 8
 #include "bg_split.hpp"
 #define BG_SPLIT 1
 #else
