@@ -105,7 +105,11 @@ typedef struct {
  * on concurrent streams.  Per-event values are reproducible for a given call and mode.
  * Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
  * event i of a class is a pure function of (seed, first_event + i, n) and of
- * ins[k] when given, so split runs reproduce an unsplit run event by event.
+ * ins[k] when given, so split runs reproduce an unsplit run event by event; for FP32
+ * n <= 8 this holds bitwise within each form (calls below 2^20 events: one kernel; from
+ * 2^20 on: two), while across the forms draws, kinematics, cut flags and observables are
+ * identical and |A|^2 and the weights agree to FP32 rounding (the compiler contracts the
+ * recursion's multiply-adds differently in the two forms).
  * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
  * counts[k] = 0 is allowed.  Errors: BG_EINVAL (ncfg < 1 or > 16, counts < 0,
  * bad parameters), BG_ENOTSUP (n or prec). */

@@ -276,6 +276,25 @@ def mixed_mode(request, gpu_lib):
     gpu_lib.set_mixed_launch(old)
 
 
+def test_two_kernel_form_matches_single_kernel(gpu_lib):
+    """FP32 n <= 8 calls of at least 2^20 events run as a kinematics and a recursion kernel,
+    smaller calls as one kernel: for the same events (the tail of a 2^20 + 37 event call,
+    and a separate call of those 5000 events) draws, kinematics, cut flags and observables
+    are identical, |A|^2 and weights equal to FP32 rounding (the two forms contract the
+    recursion's multiply-adds differently)."""
+    n, N, tail = 8, (1 << 20) + 37, 5000
+    c = cfg_c1(gpu_lib, n=n, prec=32, seed=4242)
+    outs = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12")
+    print("generate n=8 fp32 N=2^20+37 (two-kernel form) and its tail alone", flush=True)
+    big = to_np(gpu_lib.generate(c, N, outputs=outs))
+    c2 = cfg_c1(gpu_lib, n=n, prec=32, seed=4242, first_event=N - tail)
+    small = to_np(gpu_lib.generate(c2, tail, outputs=outs))
+    sub = {k: v[N - tail:] for k, v in big.items()}
+    diff = {k: int(np.sum(sub[k] != small[k])) for k in outs}
+    print("differing entries per output", diff)
+    same_events(sub, small, n, exact=False)
+
+
 def test_mixed_classes_match_single(gpu_lib, mixed_mode):
     cfgs = [cfg_c1(gpu_lib, n=n, prec=32, seed=77 + n) for n in (4, 6, 9)]
     counts = [3000, 2000, 700]
