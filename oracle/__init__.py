@@ -21,7 +21,12 @@ Everything here works on arrays batched over events; arithmetic per event is the
 plain definition, with no regrouping.
 
 Parity pins: every function is pinned by tests/test_oracle_*.py against closed
-forms, invariants or brute force, except Philox, whose bit pattern is pinned only
-by structural and statistical checks (parity unpinned against published
-known-answer vectors, which are not available here).
+forms, invariants, brute force or an independent implementation: Philox word for
+word against rocRAND's implementation of the published generator; the weight chain's
+n-dependence (helicity, ordering and colour factors, the phase-space volume) by a
+brute-force full-colour sum at n = 4, 5, the random-ordering identity and the
+recursive factorisation of phase space (tests/test_oracle_chain.py).  The values of
+non-MHV amplitudes (n >= 6) have no closed form; they are pinned by the identities
+(gauge, Ward, cyclic, reflection, U(1) decoupling, scaling, Lorentz invariance), the
+W-tensor form and a long-double evaluation.
 """

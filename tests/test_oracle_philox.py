@@ -1,15 +1,21 @@
 """Pins for the oracle's generator and draw layout.
 
-Philox's bit pattern is parity unpinned against published known-answer vectors (none
-are available here); these checks pin what a plausible slip would break: every
-counter word and key word must be mixed in (no collisions, full avalanche), the
-output must be uniform, and the draw layout must give uniform permutations and
-helicity bits.
+Philox's bit pattern is pinned word for word against an independent implementation of
+the published generator, the one in ROCm's rocRAND headers (compiled for the host from
+tests/native/philox_ref.hip), on 2^14 random (counter, key) pairs, counters with high
+words set and the all-zero / all-one inputs.  The structural checks pin what a plausible
+slip would break independently of any reference: every counter word and key word must be
+mixed in (no collisions, full avalanche), the output must be uniform, and the draw layout
+must give uniform permutations and helicity bits.
 """
 import itertools
+import os
+import shutil
+import subprocess
 from math import factorial
 
 import numpy as np
+import pytest
 from scipy import stats
 
 from oracle import draws, philox
@@ -20,6 +26,61 @@ def test_uniform01_open_interval():
     u = philox.uniform01(r)
     assert u[0] == 0.5 * 2.0**-32 and u[-1] == 1.0 - 0.5 * 2.0**-32
     assert np.all((u > 0) & (u < 1))
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCRAND_PHILOX = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+
+
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    """Runs rocRAND's Philox-4x32-10 (host build) on rows of (counter, key) words."""
+    if not (os.path.exists(HIPCC) or shutil.which(HIPCC)) or not os.path.exists(ROCRAND_PHILOX):
+        pytest.skip("hipcc or the rocRAND headers are not available")
+    exe = str(tmp_path_factory.mktemp("philox") / "philox_ref")
+    subprocess.run([HIPCC, "-O2", "--offload-arch=gfx950", "-std=c++17", os.path.join(HERE, "native", "philox_ref.hip"),
+                    "-o", exe], check=True, capture_output=True)
+
+    def run(ctr, key):
+        rows = np.concatenate([ctr, key], axis=1).astype(np.uint64)
+        inp = "\n".join(" ".join(f"{int(v):x}" for v in r) for r in rows) + "\n"
+        out = subprocess.run([exe], input=inp, check=True, capture_output=True, text=True).stdout.split()
+        return np.array([int(v, 16) for v in out], dtype=np.uint64).reshape(-1, 4).astype(np.uint32)
+    return run
+
+
+def test_philox_matches_rocrand(rocrand_philox):
+    rng = np.random.default_rng(20240611)
+    N = 1 << 14
+    ctr = rng.integers(0, 2**32, size=(N, 4), dtype=np.uint64)
+    key = rng.integers(0, 2**32, size=(N, 2), dtype=np.uint64)
+    # the event layout: small block index, event words, multiplicity tag
+    ctr[:1024, 0] = rng.integers(0, 16, 1024)
+    ctr[:1024, 3] = rng.integers(4, 13, 1024)
+    ctr[1024:1100, 1:3] = 0xFFFFFFFF                  # high counter words set
+    ctr[-2] = 0
+    key[-2] = 0
+    ctr[-1] = 0xFFFFFFFF
+    key[-1] = 0xFFFFFFFF
+    ref = rocrand_philox(ctr, key)
+    ours = np.concatenate([philox.philox4x32(ctr[i:i + 1], key[i]) for i in range(0, 64)] +
+                          [philox.philox4x32(ctr[64:], key[64:])])
+    assert ours.shape == ref.shape
+    bad = np.nonzero(np.any(ours != ref, axis=1))[0]
+    assert bad.size == 0, f"{bad.size} of {N} outputs differ, first at row {bad[:4]}"
+
+
+def test_event_words_match_rocrand(rocrand_philox):
+    # the per-event draw layout through the reference generator: counter (block, event lo,
+    # event hi, n), key (seed lo, seed hi)
+    seed, n = 0xB6000001 + (7 << 40), 8
+    ev = np.array([0, 1, 77, (1 << 32) + 5, (1 << 40) + 3], dtype=np.uint64)
+    w = draws.event_words(seed, ev, n)
+    nb = draws.n_blocks(n)
+    ctr = np.array([[b, int(e) & 0xFFFFFFFF, int(e) >> 32, n] for e in ev for b in range(nb)], dtype=np.uint64)
+    key = np.tile(np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint64), (len(ctr), 1))
+    assert np.array_equal(w.reshape(-1, 4), rocrand_philox(ctr, key))
 
 
 def _ctrs(N):
