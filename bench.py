@@ -15,7 +15,6 @@ relative error on identical events, and the forward+adjoint rate when available.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -58,11 +57,18 @@ def flops_executed(n: int) -> int:
     return tot
 
 
+def flops_real(n: int) -> int:
+    """Per-event flops of the recursion with real currents (random real polarisations) in the
+    printed form: about 51 per three-gluon and 46 per four-gluon bracket term (real dots of
+    7, axpys of 8), 5 per propagator, 20 n for the sources and the closure."""
+    L = n - 1
+    return 51 * comb(n, 3) + 46 * comb(n, 4) + 5 * (L * (L - 1) // 2 - 1) + 20 * n
+
+
 def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1002_3446_amd", "csrc"))):
-        h.update(open(os.path.join(ROOT, "paper_1002_3446_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+    """Hash of the kernel sources (the one the loaded library embeds, bg_source_hash)."""
+    from paper_1002_3446_amd.build import source_hash
+    return source_hash()
 
 
 def traffic_from_profile(kernel: str):
@@ -208,21 +214,140 @@ def live_helicities(hel, n, torch):
     return (plus >= 2) & (plus <= n - 2)
 
 
-def cpu_baseline(seconds: float = 12.0):
-    """The oracle (numpy, one thread) on a bounded sample of the same workload."""
+def host_cores() -> int:
+    """Host threads the CPU legs use: all the host's cores, at most the 16 a one-GPU share
+    of the machine provides."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+BENCH_SEED = {8: 0xB6000001, 12: 0xB6000002}
+CHUNK = 4096
+
+
+def _oracle_cfg(n):
+    from oracle import event
+    return event.config(n=n, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=BENCH_SEED[n])
+
+
+def _oracle_timed(args):
+    """Worker: oracle event generation over chunks w, w + W, ... of the n = 8 workload for
+    about `seconds`; returns (events, seconds)."""
     import numpy as np
 
     from oracle import event
-    oc = event.config(n=8, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
-    chunk = 4096
-    done = 0
+    w, W, seconds = args
+    oc = _oracle_cfg(8)
+    done, k = 0, w
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        event.generate(oc, np.arange(done, done + chunk))
-        done += chunk
-    dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="events/s", cores=1, kind="oracle",
-                sample=f"first {done} events of the n=8 workload (seed 0xB6000001), numpy float64, one thread, {dt:.1f} s")
+        event.generate(oc, np.arange(k * CHUNK, (k + 1) * CHUNK))
+        done += CHUNK
+        k += W
+    return done, time.perf_counter() - t0
+
+
+def _oracle_amp2(args):
+    """Worker: the oracle's |A|^2 and helicity words of events lo..hi-1 of a workload."""
+    import numpy as np
+
+    from oracle import event
+    from oracle.recursion import mdot
+    n, lo, hi = args
+    o = event.generate(_oracle_cfg(n), np.arange(lo, hi))
+    # the event's size for FP32 tails: the Parke-Taylor |A|^2 of its colour ordering with
+    # legs 0 and 1 of opposite helicity
+    k = o["mom_cm"] * np.array([-1.0, -1.0] + [1.0] * (n - 2))[None, :, None]
+    ko = np.take_along_axis(k, o["order"].astype(np.int64)[:, :, None], axis=1)
+    den = np.ones(len(k))
+    for t in range(n):
+        den = den * np.abs(2 * mdot(ko[:, t], ko[:, (t + 1) % n]))
+    size = np.maximum(o["amp2"], (2 * mdot(k[:, 0], k[:, 1])) ** 4 / den)
+    return o["amp2"], o["hel"], size
+
+
+def cpu_legs(seconds: float = 10.0, accuracy_events: int = 1 << 16):
+    """Runs before the GPU is touched (the worker processes are forked).  Returns the CPU
+    baseline (the oracle on all host cores and on one, a bounded sample of the n = 8
+    workload) and the oracle's |A|^2 of the first accuracy_events events of the n = 8 and
+    n = 12 workloads (the reference of the accuracy block)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    cores = host_cores()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        single = _oracle_timed((0, 1, seconds / 4))
+        res = pool.map(_oracle_timed, [(w, cores, seconds) for w in range(cores)])
+        ref = {}
+        for n in (8, 12):
+            parts = pool.map(_oracle_amp2, [(n, lo, lo + CHUNK) for lo in range(0, accuracy_events, CHUNK)])
+            ref[n] = tuple(np.concatenate([p[i] for p in parts]) for i in range(3))
+    events = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    base = dict(value=events / wall, unit="events/s", cores=cores, kind="oracle",
+                sample=f"{events} events of the n=8 workload (seed 0xB6000001, chunks of {CHUNK} events "
+                       f"interleaved over {cores} processes, numpy float64, {wall:.1f} s)",
+                single_core_events_per_s=single[0] / single[1], host_nproc=os.cpu_count(), host_cpu=cpu_model())
+    return base, ref
+
+
+def accuracy_block(bg, torch, ref):
+    """Per-event relative error of |A|^2 against the oracle (float64) on the first events of
+    the n = 8 and n = 12 workloads, FP32 and FP64 recursion, over the helicity
+    configurations whose amplitude does not vanish identically; the maximum also relative
+    to the event's size max(|A|^2, Parke-Taylor |A|^2 of its ordering), which bounds the
+    FP32 tail of events near a zero of the amplitude."""
+    import numpy as np
+    out = {}
+    for n, (oa, oh, size) in ref.items():
+        N = len(oa)
+        bits = (oh.astype(np.int64)[:, None] >> np.arange(n)) & 1
+        live = (bits.sum(1) >= 2) & (bits.sum(1) <= n - 2) & (oa > 0)
+        for prec in (32, 64):
+            c = bg.config(n, prec=prec, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=BENCH_SEED[n])
+            r = bg.generate(c, N, outputs=("amp2", "hel"))
+            g = r["amp2"].cpu().numpy()
+            gh = r["hel"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(gh, oh.astype(np.int64)), "helicity draws differ from the oracle's"
+            rel = np.abs(g[live] - oa[live]) / oa[live]
+            sc = np.abs(g[live] - oa[live]) / size[live]
+            q = np.quantile(rel, [0.5, 0.9, 0.99])
+            out[f"n{n}_fp{prec}"] = dict(p50=float(q[0]), p90=float(q[1]), p99=float(q[2]), max=float(rel.max()),
+                                         max_rel_to_event_size=float(sc.max()),
+                                         frac_within_1e12=float(np.mean(rel <= 1e-12)), events=int(live.sum()))
+    return out
+
+
+def sigma_block(bg, torch, N):
+    """sigma = sum w / N from one untimed call of the benchmark workload (events 0..N-1),
+    checked against the exact sum of that call's weights; the same events with FP64
+    recursion; their difference in units of the statistical error delta sigma."""
+    out = {}
+    for prec in (32, 64):
+        c = bg.config(8, prec=prec, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=BENCH_SEED[8])
+        r = bg.generate(c, N, outputs=("weight", "acc"))
+        acc = r["acc"].cpu().numpy()
+        exact = math.fsum(r["weight"].cpu().numpy().tolist())
+        s, s2 = acc[0] + acc[1], acc[2] + acc[3]
+        sig = s / N
+        out[prec] = dict(sigma_pb=sig, delta_sigma_pb=math.sqrt(max(s2 / N - sig * sig, 0.0) / (N - 1)),
+                         exact_sum_rel_diff=abs(s - exact) / abs(exact))
+    d = out[32]["sigma_pb"] - out[64]["sigma_pb"]
+    return {"events": N, "sigma_pb_fp32": out[32]["sigma_pb"], "delta_sigma_pb": out[64]["delta_sigma_pb"],
+            "sigma_pb_fp64": out[64]["sigma_pb"], "fp32_minus_fp64_over_delta_sigma": d / out[64]["delta_sigma_pb"],
+            "fp32_minus_fp64_rel": d / out[64]["sigma_pb"],
+            "compensated_vs_exact_sum_rel": max(out[32]["exact_sum_rel_diff"], out[64]["exact_sum_rel_diff"])}
 
 
 def main():
@@ -256,6 +381,9 @@ def main():
               "so N GPUs would run disjoint Philox event ranges and add their compensated sums.", file=sys.stderr)
         sys.exit(2)
 
+    # CPU legs first: their worker processes are forked before anything touches the GPU
+    cpu, ref = (None, None) if a.no_cpu else cpu_legs()
+
     import torch
 
     from paper_1002_3446_amd import bg
@@ -270,10 +398,10 @@ def main():
     launch_ms = sum(ms) / len(ms)
     fp = flops_plain(n)
     fe = flops_executed(n)
-    # n = 8 FP32 runs as a kinematics and a recursion kernel per chunk of 2^21 events: the
+    # FP32 n <= 8 runs as a kinematics and a recursion kernel per chunk of 2^21 events: the
     # timed unit is then the whole bg_generate call (both kernels, every chunk)
-    if n == 8:
-        kname = "k_kin<8>+k_rec<8,float>"
+    if n <= 8:
+        kname = f"k_kin<{n}>+k_rec<{n}>"
     else:
         kname = f"k_generate<{n},float>" if bg.get_lanes(n, 32) == 1 else f"k_generate_g<{n},float,2>"
     achieved = fp * N / (launch_ms * 1e-3)
@@ -303,8 +431,10 @@ def main():
         "paper_context": {"tesla_fp32_n8_events_per_s": PAPER_N8_EVENTS_PER_S,
                           "note": "paper Table 1, NVIDIA Tesla, real polarisations, LHAPDF; not the same workload"},
     }
-    acc = out["acc"].cpu().numpy()
-    line["sigma_pb_last_step"] = float((acc[0] + acc[1]) / N)
+    if n == 8:
+        line["sigma"] = sigma_block(bg, torch, N)
+    if ref is not None:
+        line["accuracy_vs_oracle"] = accuracy_block(bg, torch, ref)
 
     if a.recursion and a.no_extras:
         line["recursion_kernel"] = recursion_rate(bg, torch)
@@ -322,7 +452,7 @@ def main():
         a32, hel = r32["amp2"], r32["hel"]
         a64 = bg.generate(cfg64, 1 << 20, outputs=("amp2",))["amp2"]
         rel = ((a32 - a64).abs() / a64.abs())[live_helicities(hel, n, torch)]
-        q = torch.quantile(rel[:1 << 20].float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
+        q = torch.quantile(rel.float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
         extras["n8_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
         n12, N12 = 12, 1 << 22
         for prec in (32, 64):
@@ -339,13 +469,22 @@ def main():
         rel = ((r32["amp2"] - b64).abs() / b64.abs())[live_helicities(r32["hel"], 12, torch)]
         q = torch.quantile(rel.float(), torch.tensor([0.5, 0.9, 0.99], device=rel.device))
         extras["n12_fp32_vs_fp64_rel_err_p50_p90_p99"] = [float(x) for x in q]
+        # the paper's own sources: random real polarisation vectors (real currents)
+        for nr, Nr in ((8, N), (12, 1 << 22)):
+            cr = bg.config(nr, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=BENCH_SEED[nr], polarisation=1)
+            wr, msr, _ = run_steps(bg, torch, cr, Nr, 3, 1, outputs)
+            lm = sum(msr) / len(msr)
+            extras[f"n{nr}_realpol_fp32_events_per_s"] = Nr * 3 / wr
+            extras[f"n{nr}_realpol_fp32_launch_ms"] = lm
+            extras[f"n{nr}_realpol_fp32_frac_plain"] = flops_real(nr) * Nr / (lm * 1e-3) / PEAK_FP32
         line["recursion_kernel"] = recursion_rate(bg, torch)
         extras.update(adjoint_rate(bg, torch))
         extras.update(mixed_rate(bg, torch))
         line["extras"] = extras
 
-    if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    line["source_hash"] = bg.source_hash()
     print(json.dumps(line), flush=True)
 
 

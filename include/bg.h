@@ -63,7 +63,16 @@ typedef struct {
   double eta_max;       /* cut |eta| < eta_max */
   double dr_min;        /* cut Delta R > dr_min on every outgoing pair */
   int32_t random_order; /* 1: colour ordering drawn per event (Eq. 3.8); 0: identity */
-  int32_t reserved;     /* must be 0 */
+  int32_t polarisation; /* 0: helicity states drawn uniformly from the 2^n (the helicity word);
+                           1: random real unit vectors orthogonal to each momentum (Sec. 3,
+                           the paper's choice): eps = cos(psi) e1 + sin(psi) e2 in the
+                           transverse basis of the physical momentum, psi = 2 pi u with u
+                           from Philox (block 1 + (n-2) + ceil((n-2)/4) + k/4, word k%4 for
+                           leg k); every current is real.  2^n |A|^2 averages to the helicity
+                           sum either way, so the weight is the same formula.  bg_generate
+                           only: FP32 n = 4..12 and FP64 n = 4..8 (else BG_ENOTSUP), one lane
+                           per event, never in the persistent launch; the hel output then
+                           holds the drawn but unused helicity word */
   uint64_t seed;        /* Philox-4x32-10 key */
   uint64_t first_event; /* event index of the first event (Philox counter offset) */
 } bg_config;
@@ -94,25 +103,24 @@ typedef struct {
                         function, no sampling density); -inf when |A|^2 = 0 */
 } bg_outputs;
 
-/* Generate events of ncfg classes (Sec. 3).  One class: one launch of that multiplicity's
- * kernel (after a small setup launch that tabulates the inverse CDF of the parton density
- * when x1, x2 are sampled); n <= 8 with FP32 recursion and at least 2^20 events runs
- * instead, per chunk of up to 2^21 events, a kinematics kernel and a recursion kernel
- * joined by a stream-ordered staging buffer ((4n + 5) * 8 B per event of the chunk), or
- * the single kernel if that buffer cannot be allocated.  Several classes (mixed multiplicities): as chosen by
+/* Generate events of ncfg classes (Sec. 3).  One class: FP32 classes with n <= 8 run as a
+ * kinematics kernel and a recursion kernel joined by a staging buffer ((4n + 5) * 8 B per
+ * event, chunks of at most 2^21 events); the others as one kernel per call (after a small
+ * setup launch, once per density and device, that tabulates the inverse CDF of the parton
+ * density when x1, x2 are sampled).  Several classes (mixed multiplicities): as chosen by
  * bg_set_mixed_launch, either one after another, or the FP32 classes in one persistent
  * launch whose workgroups take tiles (largest n first) from a shared queue, or side by side
- * on concurrent streams.  Per-event values are reproducible for a given call and mode.
- * Class k gets counts[k] events with indices cfgs[k].first_event + 0..counts[k]-1;
- * event i of a class is a pure function of (seed, first_event + i, n) and of
- * ins[k] when given, so split runs reproduce an unsplit run event by event; for FP32
- * n <= 8 this holds bitwise within each form (calls below 2^20 events: one kernel; from
- * 2^20 on: two), while across the forms draws, kinematics, cut flags and observables are
- * identical and |A|^2 and the weights agree to FP32 rounding (the compiler contracts the
- * recursion's multiply-adds differently in the two forms).
+ * on concurrent streams.  Class k gets counts[k] events with indices
+ * cfgs[k].first_event + 0..counts[k]-1; event i of a class is a pure function of
+ * (seed, first_event + i, n) and of ins[k] when given, and its per-event outputs are
+ * bitwise the same for every call size, split of the event range and launch mode (the
+ * persistent launch evaluates n = 9 with two lanes per event, as bg_set_lanes(9, 32, 2)
+ * does); the totals agree within the compensated-sum bound.
+ * Device workspace (partials, staging) is allocated stream-ordered from a library-owned
+ * memory pool per device, which keeps up to 4 GiB reserved between calls.
  * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
  * counts[k] = 0 is allowed.  Errors: BG_EINVAL (ncfg < 1 or > 16, counts < 0,
- * bad parameters), BG_ENOTSUP (n or prec). */
+ * bad parameters), BG_ENOTSUP (n, prec, or a lane form not built), BG_ENOMEM. */
 int bg_generate(const bg_config *cfgs, int ncfg, const int64_t *counts,
                 const bg_inputs *ins, const bg_outputs *outs, void *stream);
 
@@ -135,7 +143,7 @@ int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
  * gout [N] (dL/dlog w, may be NULL = all ones); grad_u [N][4(n-2)], grad_x [N][2]
  * (zeros when use_pdf = 0) receive gout * d log w_int; logw [N] optional.
  * Events with |A|^2 = 0 get log w = -inf and zero gradients.
- * Supported for n = 4..10 (BG_ENOTSUP for n = 11, 12). */
+ * Supported for n = 4..8 (BG_ENOTSUP for n = 9..12, and for real polarisations). */
 int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const double *x12,
                  const uint32_t *hel, const uint8_t *order, const double *gout,
                  double *grad_u, double *grad_x, double *logw, void *stream);
@@ -159,10 +167,10 @@ int bg_set_launch(int n, int prec, int block, int tile_iters);
 int bg_get_launch(int n, int prec, int *block, int *tile_iters);
 
 /* Lanes of a wave that share one event in the single-class kernels of (n, prec) (bg_generate
- * and bg_amp2; the persistent multi-class kernel uses one lane per event, and bg_amp2_grad
- * uses two for the recursion adjoint of FP32 n = 6..8 and one otherwise, independent of this):
- * 1, or 2 where the library holds the two-lane form (FP32 n >= 9, FP64 n >= 6; else
- * BG_ENOTSUP); 0 restores the default (2 for FP32 n >= 10 and FP64 n >= 7, else 1).  With
+ * and bg_amp2; bg_amp2_grad uses two for the recursion adjoint of FP32 n = 6..8 and one
+ * otherwise, independent of this): 1 where the library holds the one-lane form (FP32
+ * n <= 9, FP64 n <= 6), 2 where it holds the two-lane form (FP32 n >= 9, FP64 n >= 6), else
+ * BG_ENOTSUP; 0 restores the default (2 for FP32 n >= 10 and FP64 n >= 7, else 1).  With
  * two lanes each holds two of the four Lorentz components of every current: half the
  * registers, at the price of cross-lane sums in every Minkowski product.  Affects speed
  * only: |A|^2 agrees to the recursion precision's rounding between the forms. */
@@ -171,16 +179,18 @@ int bg_get_lanes(int n, int prec, int *lanes);
 
 /* Strategy for bg_generate calls with several classes (process-wide setting):
  *   0  each class's single-class kernel, one after another on the caller's stream;
- *   1  (default) the FP32 classes in one persistent launch (FP64 classes as in 0);
+ *   1  (default) the FP32 classes in one persistent launch (FP64 classes as in 0): the
+ *      kinematics of the classes with n <= 8 in one kernel, then one persistent kernel
+ *      whose one-wave workgroups take tiles, largest n first, from a shared queue (n >= 9
+ *      generated two lanes per event, n <= 8 finished from the staged kinematics), then one
+ *      reduction per class; falls back to 0 when the staging would exceed 8 GiB;
  *   2  the classes' single-class kernels on up to four library-owned side streams (created
  *      once per device at default priority, kept until the process ends), forked from and
  *      joined back into the caller's stream with events, so that classes too small to
  *      fill the GPU run side by side.
- * The persistent kernel balances load across classes but carries the register allocation
- * of the largest multiplicity (one wave per SIMD for every class); the autotuner times
- * the three and records the fastest.  Per-event draws, kinematics and cut flags are
- * identical in every mode; |A|^2 agrees to the recursion precision's rounding (modes 0
- * and 2 run the same kernels and agree exactly).  Errors: BG_EINVAL for another value. */
+ * The autotuner times the three and records the fastest.  Per-event outputs are bitwise
+ * identical in every mode (the persistent launch uses the two-lane form for n = 9);
+ * totals agree within the compensated-sum bound.  Errors: BG_EINVAL for another value. */
 int bg_set_mixed_launch(int mode);
 int bg_get_mixed_launch(void);
 
@@ -189,6 +199,10 @@ const char *bg_strerror(int status);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int bg_version(void);
+
+/* Identity of the sources the library was built from: the first 16 hexadecimal digits of a
+ * sha256 over the kernel sources and this header (static string). */
+const char *bg_source_hash(void);
 
 #ifdef __cplusplus
 }

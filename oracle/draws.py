@@ -12,6 +12,8 @@ for those draws so that every event is a pure function of (seed, event index, n)
                         word 3 unused
   block 1 .. n-2      : the four RAMBO uniforms (rho1..rho4) of final gluon 3 .. n
   block n-1 ...       : shuffle words r_t, consumed for t = n-2, n-3, ..., 1
+  block n_blocks(n)+k/4, word k%4 (real polarisations only): the angle of leg k,
+                        psi_k = 2 pi u_k, k = 0 .. n-1
 
 Colour ordering (Fisher-Yates on the 0-based legs 1..n-1, leg 0 always closes):
   a = [1, 2, ..., n-1];  for t = n-2 down to 1:  j = (r_t * (t+1)) >> 32; swap a[t], a[j]
@@ -29,11 +31,16 @@ def n_blocks(n: int) -> int:
     return 1 + nf + (n - 2 + 3) // 4
 
 
-def event_words(seed: int, events: np.ndarray, n: int) -> np.ndarray:
-    """[B, 4*n_blocks] uint32 words of the given event indices."""
+def angle_blocks(n: int) -> int:
+    return (n + 3) // 4
+
+
+def event_words(seed: int, events: np.ndarray, n: int, real_pol: bool = False) -> np.ndarray:
+    """[B, 4*blocks] uint32 words of the given event indices (blocks = n_blocks, plus the
+    angle blocks with real polarisations)."""
     events = np.asarray(events, dtype=np.uint64)
     B = events.shape[0]
-    nb = n_blocks(n)
+    nb = n_blocks(n) + (angle_blocks(n) if real_pol else 0)
     ctr = np.zeros((B, nb, 4), dtype=np.uint64)
     ctr[:, :, 0] = np.arange(nb, dtype=np.uint64)[None, :]
     ctr[:, :, 1] = (events & np.uint64(0xFFFFFFFF))[:, None]
@@ -42,6 +49,12 @@ def event_words(seed: int, events: np.ndarray, n: int) -> np.ndarray:
     key = np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint64)
     out = philox4x32(ctr.reshape(-1, 4), key)
     return out.reshape(B, nb * 4)
+
+
+def polarisation_angles(words: np.ndarray, n: int) -> np.ndarray:
+    """Words of event_words(..., real_pol=True) -> [B, n] angles psi_k = 2 pi u_k."""
+    a = 4 * n_blocks(n)
+    return 2.0 * np.pi * uniform01(words[:, a:a + n])
 
 
 def split_draws(words: np.ndarray, n: int, random_order: bool = True):

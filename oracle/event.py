@@ -13,7 +13,8 @@ log_weight_int() / log_weight_grad():
 
 Configuration dictionaries use the keys of the C-ABI's bg_config:
   n, prec (ignored: the oracle is always double), sqrt_s, use_pdf, pdf_a, pdf_b,
-  tau_min, alpha_s, pt_min, eta_max, dr_min, random_order, seed, first_event.
+  tau_min, alpha_s, pt_min, eta_max, dr_min, random_order, seed, first_event,
+  polarisation (0: helicity states, 1: random real unit vectors, Sec. 3).
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import numpy as np
 
 from . import cuts as _cuts
 from . import draws, pdf
-from .helicity import polarisation
+from .helicity import linear_polarisation, polarisation
 from .ops import NP64, TorchOps
 from .rambo import beams, boost_z, rambo
 from .recursion import amp2_from_m, mdot, ordered_amplitude
@@ -31,7 +32,7 @@ from .weight import HBARC2_PB, NC, weight
 
 DEFAULTS = dict(prec=64, sqrt_s=14000.0, use_pdf=1, pdf_a=-1.3, pdf_b=5, tau_min=0.0,
                 alpha_s=0.118, pt_min=20.0, eta_max=2.5, dr_min=0.4, random_order=1,
-                seed=0, first_event=0)
+                seed=0, first_event=0, polarisation=0)
 
 
 def config(**kw) -> dict:
@@ -65,6 +66,17 @@ def amp2(mom, hel, order, ops=NP64):
     return amp2_from_m(ordered_amplitude(k, e), mom.shape[1], ops)
 
 
+def amp2_real(mom, psi, order, ops=NP64):
+    """|A(sigma; eps_psi)|^2 with real polarisation vectors at angles psi [B, n]."""
+    mom = ops.asarray(mom)
+    n = mom.shape[1]
+    eps = linear_polarisation(mom, ops.asarray(psi), ops)
+    sign = ops.asarray(np.array([-1.0, -1.0] + [1.0] * (n - 2)))
+    k = mom * sign[None, :, None]
+    m = ordered_amplitude(ops.gather_legs(k, order), ops.gather_legs(eps, order))
+    return m * m * ops.const(2.0 ** -(n - 2))
+
+
 def _cat(b, p):
     return np.concatenate([b, p], axis=1) if isinstance(p, np.ndarray) else __import__("torch").cat([b, p], dim=1)
 
@@ -93,8 +105,9 @@ def kinematics(cfg: dict, rho, x12, ops=NP64, cm=False):
 def generate(cfg: dict, events) -> dict:
     """Full event generation for the given absolute event indices (float64)."""
     n = cfg["n"]
+    real = bool(cfg.get("polarisation", 0))
     events = np.asarray(events, dtype=np.uint64)
-    words = draws.event_words(cfg["seed"], events, n)
+    words = draws.event_words(cfg["seed"], events, n, real_pol=real)
     ux, rho, hel, order = draws.split_draws(words, n, bool(cfg["random_order"]))
     if cfg["use_pdf"]:
         a, b, tau = cfg["pdf_a"], int(cfg["pdf_b"]), cfg["tau_min"]
@@ -105,11 +118,12 @@ def generate(cfg: dict, events) -> dict:
         ratio = 1.0
     mom, s_hat, mom_cm = kinematics(cfg, rho, x12, cm=True)
     cut = _cuts.cuts(mom[:, 2:], cfg["pt_min"], cfg["eta_max"], cfg["dr_min"])
-    a2 = amp2(mom_cm, hel, order)
+    psi = draws.polarisation_angles(words, n) if real else None
+    a2 = amp2_real(mom_cm, psi, order) if real else amp2(mom_cm, hel, order)
     w = weight(a2, s_hat, n, cfg["alpha_s"], ratio, cut["pass_"])
     return dict(x12=x12, rho=rho, hel=hel, order=order, mom=mom, mom_cm=mom_cm, s_hat=s_hat, amp2=a2,
                 weight=w, pass_=cut["pass_"], ht=cut["ht"], rmin=cut["rmin"],
-                margin=cut["margin"], words=words)
+                margin=cut["margin"], words=words, psi=psi)
 
 
 def log_const(n: int, alpha_s: float) -> float:

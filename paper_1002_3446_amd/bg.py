@@ -18,6 +18,19 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1002_3446_amd.build`")
 
 _lib = ctypes.CDLL(LIB_PATH)
+_lib.bg_source_hash.restype = ctypes.c_char_p
+_lib.bg_source_hash.argtypes = []
+
+
+def _expected_hash() -> str:
+    from .build import source_hash
+    return source_hash()
+
+
+SOURCE_HASH = _lib.bg_source_hash().decode()
+if SOURCE_HASH != _expected_hash():
+    raise ImportError(f"{LIB_PATH} was built from other sources (library {SOURCE_HASH}, tree {_expected_hash()}): "
+                      "rebuild it with `python -m paper_1002_3446_amd.build`")
 
 BG_OK, BG_EINVAL, BG_ENOTSUP, BG_EHIP, BG_ENOMEM = 0, -1, -2, -3, -4
 
@@ -28,7 +41,7 @@ class BgConfig(ctypes.Structure):
         ("use_pdf", ctypes.c_int32), ("pdf_b", ctypes.c_int32), ("pdf_a", ctypes.c_double),
         ("tau_min", ctypes.c_double), ("alpha_s", ctypes.c_double), ("pt_min", ctypes.c_double),
         ("eta_max", ctypes.c_double), ("dr_min", ctypes.c_double), ("random_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("first_event", ctypes.c_uint64),
+        ("polarisation", ctypes.c_int32), ("seed", ctypes.c_uint64), ("first_event", ctypes.c_uint64),
     ]
 
 
@@ -78,6 +91,11 @@ def version() -> int:
     return _lib.bg_version()
 
 
+def source_hash() -> str:
+    """Hash of the sources the loaded library was built from (equal to the tree's)."""
+    return SOURCE_HASH
+
+
 def strerror(status: int) -> str:
     return _lib.bg_strerror(status).decode()
 
@@ -85,9 +103,10 @@ def strerror(status: int) -> str:
 def config(n: int, prec: int = 32, sqrt_s: float = 14000.0, use_pdf: int = 1, pdf_a: float = -1.3,
            pdf_b: int = 5, tau_min: float = 0.0, alpha_s: float = 0.118, pt_min: float = 20.0,
            eta_max: float = 2.5, dr_min: float = 0.4, random_order: int = 1, seed: int = 0,
-           first_event: int = 0) -> BgConfig:
+           first_event: int = 0, polarisation: int = 0) -> BgConfig:
+    """polarisation: 0 helicity states, 1 random real unit vectors (real currents)."""
     return BgConfig(n, prec, sqrt_s, use_pdf, pdf_b, pdf_a, tau_min, alpha_s, pt_min, eta_max, dr_min,
-                    random_order, 0, seed, first_event)
+                    random_order, polarisation, seed, first_event)
 
 
 def _ptr(t, dtype, shape, name):

@@ -1,5 +1,7 @@
-"""Builds libbg.so for gfx950 in-tree: one object per multiplicity (kernels fully unrolled
-per n) plus the C-ABI layer, compiled in parallel with hipcc, then linked shared.
+"""Builds libbg.so for gfx950 in-tree: one object per kernel (kind, multiplicity, precision,
+lane form; kernels fully unrolled per n), the persistent multi-class kernel, and the C-ABI
+layer, compiled in parallel with hipcc, then linked shared.  The C-ABI layer embeds a hash
+of the sources (source_hash), which the binding checks before it uses the library.
 
 Usage: python -m paper_1002_3446_amd.build [--jobs J]
 """
@@ -7,12 +9,15 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
+import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
+HEADER = os.path.join(PKG, "..", "include", "bg.h")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -21,66 +26,89 @@ FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay disabled (only scalar FP32 VALU forms are emitted)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # the recursion is unrolled completely per multiplicity so currents stay in registers
-    "-mllvm", "-pragma-unroll-threshold=100000000",
+    # LLVM's CodeGenPrepare pass is quadratic on the recursion's straight-line code (half the
+    # compile time of a unit) and changes nothing in its machine code: skipped
+    "-mllvm", "-disable-cgp",
 ]
 
 
-def _compile(src: str, obj: str, defines: list[str]) -> str:
+def source_hash() -> str:
+    """sha256 (first 16 hex digits) over the kernel sources in csrc/ (sorted by name) and the
+    C header: the identity a built library carries and the binding checks."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    h.update(open(HEADER, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, obj: str, defines: list[str]) -> tuple[str, float]:
     cmd = [HIPCC, *FLAGS, *defines, "-c", src, "-o", obj]
+    t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {obj}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    return obj
+    return obj, time.time() - t0
 
 
 KINDS = (0, 1, 2)  # 0 generate, 1 amp2, 2 gradient
-GRAD_MAX_N = 10    # the fully unrolled adjoint of n = 11, 12 would need 4-8x the register file
+GRAD_MAX_N = 8     # beyond, the fully unrolled one-lane adjoint spills kilobytes per lane and takes
+                   # most of the build time
+
+
+def has_one_lane(n: int, p: int) -> bool:
+    return n <= 9 if p == 32 else n <= 6
+
+
+def has_lane_pairs(n: int, p: int) -> bool:
+    return n >= 9 if p == 32 else n >= 6
+
+
+def has_real_pol(n: int, p: int) -> bool:
+    return n <= 12 if p == 32 else n <= 8
 
 
 def units_for(ns, precs=(32, 64), kinds=KINDS):
-    units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"), [], 0),
+    """(source, object, defines, expected cost) of every unit; the costliest start first."""
+    units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"),
+              [f'-DBG_SOURCE_HASH="{source_hash()}"'], 0),
              (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0)]
-    # the persistent multi-class kernel holds every multiplicity: start it first
-    units.append((os.path.join(CSRC, "bg_multi.hip"), os.path.join(OUT_DIR, "bg_multi_p32.o"), [], 1000))
+    if set(range(4, 13)) <= set(ns) and 32 in precs:
+        units.append((os.path.join(CSRC, "bg_multi.hip"), os.path.join(OUT_DIR, "bg_multi_p32.o"), [], 1000))
     for n in ns:
         for p in precs:
             for k in kinds:
-                if k == 2 and n > GRAD_MAX_N:
-                    continue
-                obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}.o")
-                units.append((os.path.join(CSRC, "bg_inst.hip"), obj,
-                              [f"-DBG_N={n}", f"-DBG_PREC={p}", f"-DBG_KIND={k}"], n * (2 if p == 64 else 1)))
-    # the largest multiplicities take longest to compile: start them first
+                if k == 2:
+                    if n > GRAD_MAX_N:
+                        continue
+                    forms = (1,)
+                else:
+                    forms = tuple(f for f, ok in ((1, has_one_lane(n, p)), (2, has_lane_pairs(n, p)),
+                                                  (3, k == 0 and has_real_pol(n, p))) if ok)
+                for f in forms:
+                    obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}_f{f}.o")
+                    cost = n ** 3 * (2 if p == 64 else 1) * (4 if k == 2 else 1)
+                    units.append((os.path.join(CSRC, "bg_inst.hip"), obj,
+                                  [f"-DBG_N={n}", f"-DBG_PREC={p}", f"-DBG_KIND={k}", f"-DBG_FORM={f}"], cost))
     units.sort(key=lambda u: -u[3])
     return units
 
 
-def _deps_mtime(src: str) -> float:
-    """Newest modification time of a unit's inputs: its own source, every header in csrc/
-    and include/bg.h (other .hip files are not inputs)."""
-    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
-    hdrs.append(os.path.join(PKG, "..", "include", "bg.h"))
-    return max(os.path.getmtime(f) for f in hdrs + [src])
-
-
-def build(jobs: int | None = None, verbose: bool = True, ns=range(4, 13), incremental: bool = False) -> str:
-    """Compiles every unit for the multiplicities ns and links libbg.so.  incremental=True
-    keeps objects newer than their unit's inputs (developer convenience; the default
-    rebuilds all)."""
+def build(jobs: int | None = None, verbose: bool = True, ns=range(4, 13)) -> str:
+    """Compiles every unit for the multiplicities ns and links libbg.so (always a full build)."""
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     units = units_for(list(ns))
-    if incremental:
-        done = [u for u in units if os.path.exists(u[1]) and os.path.getmtime(u[1]) > _deps_mtime(u[0])]
-        units_todo = [u for u in units if u not in done]
-        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-            list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units_todo))
-        objs = [u[1] for u in units]
-        return _link(objs, verbose)
+    t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units))
-    return _link(objs, verbose)
+        done = list(ex.map(lambda u: _compile(u[0], u[1], u[2]), units))
+    if verbose:
+        slow = sorted(done, key=lambda d: -d[1])[:3]
+        print(f"compiled {len(done)} units in {time.time() - t0:.0f} s (slowest: "
+              + ", ".join(f"{os.path.basename(o)} {t:.0f} s" for o, t in slow) + ")", file=sys.stderr)
+    return _link([d[0] for d in done], verbose)
 
 
 def _link(objs, verbose) -> str:
@@ -91,7 +119,7 @@ def _link(objs, verbose) -> str:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
+        print(f"built {LIB} (sources {source_hash()})", file=sys.stderr)
     return LIB
 
 
@@ -100,6 +128,5 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--ns", type=str, default="4,5,6,7,8,9,10,11,12",
                     help="comma-separated multiplicities to build (others report BG_ENOTSUP)")
-    ap.add_argument("--incremental", action="store_true", help="reuse objects newer than their unit's inputs")
     a = ap.parse_args()
-    build(a.jobs, ns=[int(x) for x in a.ns.split(",")], incremental=a.incremental)
+    build(a.jobs, ns=[int(x) for x in a.ns.split(",")])

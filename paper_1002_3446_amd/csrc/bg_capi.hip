@@ -12,22 +12,28 @@
 #include "../../include/bg.h"
 #include "bg_launch.hpp"
 
-// Launchers of every (kind, n, prec) translation unit; weak, so a library built for a
-// subset of multiplicities reports BG_ENOTSUP for the others.
+// Launchers of every (kind, n, prec, form) translation unit; weak, so that forms and
+// multiplicities the library was not built with report BG_ENOTSUP.
 #define BG_DECL_ONE(N, P)                                                                                  \
-  __attribute__((weak)) hipError_t launch_generate_n##N##_p##P##_k0(const GenClass&, double*, int,        \
+  __attribute__((weak)) hipError_t launch_generate_n##N##_p##P##_k0(const GenClass&, const GenWork&, int,  \
                                                                     hipStream_t);                         \
   __attribute__((weak)) hipError_t launch_amp2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*,  \
                                                                 const uint8_t*, double*, int, hipStream_t); \
   __attribute__((weak)) hipError_t launch_grad_n##N##_p##P##_k2(const GradArgs&, int, hipStream_t);       \
-  __attribute__((weak)) hipError_t launch_generate2_n##N##_p##P##_k0(const GenClass&, double*, int,       \
+  __attribute__((weak)) hipError_t launch_generate2_n##N##_p##P##_k0(const GenClass&, const GenWork&, int, \
                                                                      hipStream_t);                        \
   __attribute__((weak)) hipError_t launch_amp2_2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*, \
-                                                                  const uint8_t*, double*, int, hipStream_t);
+                                                                  const uint8_t*, double*, int, hipStream_t); \
+  __attribute__((weak)) hipError_t launch_generate_real_n##N##_p##P##_k0(const GenClass&, const GenWork&, int, \
+                                                                         hipStream_t);
 #define BG_DECL(N) BG_DECL_ONE(N, 32) BG_DECL_ONE(N, 64)
 namespace bgk {
 BG_DECL(4) BG_DECL(5) BG_DECL(6) BG_DECL(7) BG_DECL(8) BG_DECL(9) BG_DECL(10) BG_DECL(11) BG_DECL(12)
 }
+
+#ifndef BG_SOURCE_HASH
+#define BG_SOURCE_HASH "unknown"
+#endif
 
 namespace {
 
@@ -35,9 +41,9 @@ using namespace bgk;
 
 #define BG_ROW(N)                                                                                       \
   {{launch_generate_n##N##_p32_k0, launch_amp2_n##N##_p32_k1, launch_grad_n##N##_p32_k2,                \
-    launch_generate2_n##N##_p32_k0, launch_amp2_2_n##N##_p32_k1},                                       \
+    launch_generate2_n##N##_p32_k0, launch_amp2_2_n##N##_p32_k1, launch_generate_real_n##N##_p32_k0},   \
    {launch_generate_n##N##_p64_k0, launch_amp2_n##N##_p64_k1, launch_grad_n##N##_p64_k2,                \
-    launch_generate2_n##N##_p64_k0, launch_amp2_2_n##N##_p64_k1}}
+    launch_generate2_n##N##_p64_k0, launch_amp2_2_n##N##_p64_k1, launch_generate_real_n##N##_p64_k0}}
 
 const Launchers* table(int n, int prec) {
   static const Launchers t[9][2] = {BG_ROW(4),  BG_ROW(5),  BG_ROW(6), BG_ROW(7), BG_ROW(8),
@@ -146,7 +152,7 @@ double binom(int b, int k) {
 
 int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_outputs* out, GenClass& G) {
   if (c.n < 4 || c.n > 12 || (c.prec != 32 && c.prec != 64)) return BG_ENOTSUP;
-  if (count < 0 || c.reserved != 0 || !(c.sqrt_s > 0) || (c.use_pdf != 0 && c.use_pdf != 1) ||
+  if (count < 0 || (c.polarisation != 0 && c.polarisation != 1) || !(c.sqrt_s > 0) || (c.use_pdf != 0 && c.use_pdf != 1) ||
       (c.random_order != 0 && c.random_order != 1) || !(c.alpha_s > 0) || !(c.pt_min >= 0) ||
       !(c.eta_max > 0) || !(c.dr_min >= 0))
     return BG_EINVAL;
@@ -157,6 +163,7 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
   G.key1 = (uint32_t)(c.seed >> 32);
   G.use_pdf = c.use_pdf;
   G.random_order = c.random_order;
+  G.polarisation = c.polarisation;
   G.sqrt_s = c.sqrt_s;
   G.pt_min = c.pt_min;
   G.eta_max = c.eta_max;
@@ -218,10 +225,93 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
 
 int from_hip(hipError_t e) { return e == hipSuccess ? BG_OK : BG_EHIP; }
 
-// Inverse-CDF tables of the parton density (layout at pdf_sample): built on the host the
-// first time a (pdf_a, pdf_b, tau) triple is used on a device, copied to device memory and
-// kept, immutable, until the process ends (10.5 KB each).
-int pdf_table(const PdfParams& P, const double** out) {
+// ----------------------------------------------------------------------------------------
+// Device workspace.  Every per-call buffer (compensated-sum partials, staging between the
+// kinematics and recursion kernels, the gradient's intermediate adjoints, the multi-class
+// work list) is allocated stream-ordered on the caller's stream from a memory pool the
+// library creates once per device; the pool keeps up to kPoolKeep bytes reserved between
+// calls, so that repeated calls do not map fresh device memory each time.
+// ----------------------------------------------------------------------------------------
+constexpr uint64_t kPoolKeep = uint64_t(4) << 30;
+
+hipMemPool_t device_pool() {
+  static std::mutex mu;
+  static hipMemPool_t pools[64];
+  static int state[64] = {0};  // 0 untried, 1 ready, -1 unavailable (use the default pool)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (state[dev] == 0) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    state[dev] = -1;
+    if (hipMemPoolCreate(&pools[dev], &props) == hipSuccess) {
+      uint64_t keep = kPoolKeep;
+      (void)hipMemPoolSetAttribute(pools[dev], hipMemPoolAttrReleaseThreshold, &keep);
+      state[dev] = 1;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  return state[dev] == 1 ? pools[dev] : nullptr;
+}
+
+int ws_alloc(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  if (bytes == 0) return BG_OK;
+  hipMemPool_t pool = device_pool();
+  const hipError_t e = pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return BG_ENOMEM;
+  }
+  return BG_OK;
+}
+
+// Stream-ordered device workspace, released on the stream when the owner goes out of scope.
+struct Workspace {
+  void* p = nullptr;
+  hipStream_t s;
+  ~Workspace() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+  double* d() const { return static_cast<double*>(p); }
+};
+
+// ----------------------------------------------------------------------------------------
+// Inverse-CDF tables of the parton density (layout at pdf_sample).  The table is evaluated
+// by a small device kernel (k_pdf_table), the same one the allocation-free entry point uses,
+// so that both give bitwise the same parton fractions; the host evaluates it once as well,
+// only to reject densities whose table would not be finite.  One table per distinct
+// (pdf_a, pdf_b, tau) and device, built at first use (which synchronises the caller's stream
+// once) and kept, immutable, until the process ends (10.5 KB each).
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_pdf_table(PdfParams P, double* out) {
+  const int seg = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (seg < kPdfSegs) pdf_table_segment(P, seg, out + 4 * seg);
+}
+
+hipError_t launch_pdf_table(const PdfParams& P, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pdf_table, dim3((kPdfSegs + 63) / 64), dim3(64), 0, s, P, out);
+  return hipGetLastError();
+}
+
+bool pdf_table_finite_host(const PdfParams& P) {
+  double seg[4];
+  for (int k = 0; k < kPdfSegs; ++k) {
+    pdf_table_segment(P, k, seg);
+    for (double v : seg)
+      if (!std::isfinite(v)) return false;
+  }
+  return true;
+}
+
+int pdf_table(const PdfParams& P, const double** out, hipStream_t s) {
   struct Entry {
     int dev;
     double a, tau;
@@ -238,16 +328,13 @@ int pdf_table(const PdfParams& P, const double** out) {
       *out = e.d;
       return BG_OK;
     }
-  std::vector<double> h((size_t)kPdfSegs * 4);
-  for (int seg = 0; seg < kPdfSegs; ++seg) pdf_table_segment(P, seg, h.data() + 4 * seg);
-  for (double v : h)
-    if (!std::isfinite(v)) return BG_EINVAL;
+  if (!pdf_table_finite_host(P)) return BG_EINVAL;
   double* d = nullptr;
-  if (hipMalloc((void**)&d, h.size() * sizeof(double)) != hipSuccess) {
+  if (hipMalloc((void**)&d, (size_t)kPdfSegs * 4 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     return BG_ENOMEM;
   }
-  if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+  if (launch_pdf_table(P, d, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(d);
     return BG_EHIP;
   }
@@ -256,41 +343,71 @@ int pdf_table(const PdfParams& P, const double** out) {
   return BG_OK;
 }
 
-// Stream-ordered device workspace, released on the stream when the owner goes out of scope.
-struct Workspace {
-  double* p = nullptr;
-  hipStream_t s;
-  ~Workspace() {
-    if (p) (void)hipFreeAsync(p, s);
-  }
+// ----------------------------------------------------------------------------------------
+// Single-class launches.
+// ----------------------------------------------------------------------------------------
+// Staging of the split form: chunks of at most kStageChunk events (at n = 8, 621 MB).
+constexpr int64_t kStageChunk = int64_t(1) << 21;
+
+struct ClassPlan {
+  int lanes, block;
+  int64_t nblocks;  // workgroups = compensated partials
+  GenerateFn fn;
 };
 
-// Persistent multi-class launch over the classes ks (all of recursion precision prec):
-// tile list ordered by decreasing n, class table and tiles copied to a stream-ordered
-// workspace together with the zeroed tile counter.
-int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* outs, std::vector<int> ks, int prec,
+int plan_class(const bg_config& c, const GenClass& G, ClassPlan& P) {
+  const Launchers* L = table(c.n, c.prec);
+  P.lanes = c.polarisation ? 1 : lanes_of(c.n, c.prec);
+  P.fn = c.polarisation ? L->generate_real : (P.lanes == 2 ? L->generate2 : L->generate);
+  if (!P.fn) return BG_ENOTSUP;
+  P.block = (P.lanes == 1 && split_form(c.n, c.prec)) ? kLdsLanes : shape_of(c.n, c.prec).block;
+  P.nblocks = (P.lanes * G.count + P.block - 1) / P.block;
+  return BG_OK;
+}
+
+// Persistent multi-class launch over the FP32 classes ks (see bg_multi.hip).  Returns
+// BG_ENOTSUP, with nothing enqueued, when the classes' staging would exceed
+// kMultiStageMax (the caller then runs them one after another).
+constexpr size_t kMultiStageMax = size_t(8) << 30;
+
+int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* outs, const std::vector<int>& ks,
                    hipStream_t s) {
-  std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return cfgs[a].n > cfgs[b].n; });
-  std::vector<MultiClass> mcs(ks.size());
-  std::vector<Tile> tiles;
-  int block = 256;
-  for (size_t c = 0; c < ks.size(); ++c) {
-    const int k = ks[c];
-    const Shape sh = shape_of(cfgs[k].n, prec);
-    block = std::min(block, sh.block);
-  }
-  for (size_t c = 0; c < ks.size(); ++c) {
-    const int k = ks[c];
-    const Shape sh = shape_of(cfgs[k].n, prec);
-    const int64_t tile = (int64_t)block * sh.tile_iters;
+  std::vector<int> order;  // staged classes first (kinematics workgroup order), then the others
+  for (int k : ks)
+    if (split_form(cfgs[k].n, 32)) order.push_back(k);
+  const int nstaged = (int)order.size();
+  for (int k : ks)
+    if (!split_form(cfgs[k].n, 32)) order.push_back(k);
+  std::vector<MultiClass> mcs(order.size());
+  int64_t kin_blocks = 0, stage_words = 0;
+  for (size_t c = 0; c < order.size(); ++c) {
+    const int k = order[c];
     MultiClass& m = mcs[c];
     std::memset(&m, 0, sizeof(m));
     m.C = G[k];
     m.n = cfgs[k].n;
     m.acc = outs[k].acc;
+    m.staged = (int)c < nstaged;
+    if (m.staged) {
+      m.kin_begin = kin_blocks;
+      m.stage_off = stage_words;
+      kin_blocks += (G[k].count + kKinBlock - 1) / kKinBlock;
+      stage_words += (G[k].count + kLdsLanes - 1) / kLdsLanes * kLdsLanes * split_words(m.n);
+    }
+  }
+  if ((size_t)stage_words * sizeof(double) > kMultiStageMax) return BG_ENOTSUP;
+  // tiles by decreasing n: the most expensive events start first
+  std::vector<int> byn(order.size());
+  for (size_t c = 0; c < byn.size(); ++c) byn[c] = (int)c;
+  std::stable_sort(byn.begin(), byn.end(), [&](int a, int b) { return mcs[a].n > mcs[b].n; });
+  std::vector<Tile> tiles;
+  for (int c : byn) {
+    MultiClass& m = mcs[c];
+    const int per_iter = m.staged ? kMultiBlock : kMultiBlock / 2;
+    const int64_t tile = (int64_t)per_iter * shape_of(m.n, 32).tile_iters;
     m.tile_begin = (int)tiles.size();
-    for (int64_t f = 0; f < G[k].count; f += tile)
-      tiles.push_back(Tile{f, (int32_t)std::min<int64_t>(tile, G[k].count - f), (int32_t)c});
+    for (int64_t f = 0; f < m.C.count; f += tile)
+      tiles.push_back(Tile{f, (int32_t)std::min<int64_t>(tile, m.C.count - f), (int32_t)c});
     m.tile_end = (int)tiles.size();
   }
   if (tiles.empty()) return BG_OK;
@@ -303,23 +420,19 @@ int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* o
   std::vector<unsigned char> blob(o_part, 0);  // classes, tiles and a zero counter
   std::memcpy(blob.data() + o_cls, mcs.data(), mcs.size() * sizeof(MultiClass));
   std::memcpy(blob.data() + o_tiles, tiles.data(), tiles.size() * sizeof(Tile));
-  unsigned char* ws = nullptr;
-  if (hipMallocAsync((void**)&ws, bytes, s) != hipSuccess) {
-    (void)hipGetLastError();
-    return BG_ENOMEM;
-  }
+  Workspace ws{nullptr, s}, stage{nullptr, s};
+  int st = ws_alloc(&ws.p, bytes, s);
+  if (st == BG_OK) st = ws_alloc(&stage.p, (size_t)stage_words * sizeof(double), s);
+  if (st != BG_OK) return st;
+  unsigned char* w = static_cast<unsigned char*>(ws.p);
   // pageable source: the copy is staged before hipMemcpyAsync returns, so blob may go
-  int st = from_hip(hipMemcpyAsync(ws, blob.data(), o_part, hipMemcpyHostToDevice, s));
-  if (st == BG_OK) {
-    const int grid = cu_count() * (256 / block);
-    (void)prec;
-    st = from_hip(launch_generate_multi_p32((const MultiClass*)(ws + o_cls), (int)mcs.size(), (const Tile*)(ws + o_tiles),
-                         (int)tiles.size(), (int*)(ws + o_ctr), (double*)(ws + o_part), grid, block, s));
-  }
-  (void)hipFreeAsync(ws, s);
-  return st;
+  st = from_hip(hipMemcpyAsync(w, blob.data(), o_part, hipMemcpyHostToDevice, s));
+  if (st != BG_OK) return st;
+  const int grid = cu_count() * 4;  // one one-wave workgroup per SIMD
+  return from_hip(launch_generate_multi_p32((const MultiClass*)(w + o_cls), (int)mcs.size(), nstaged, kin_blocks,
+                                            (const Tile*)(w + o_tiles), (int)tiles.size(), (int*)(w + o_ctr),
+                                            stage.d(), (double*)(w + o_part), grid, s));
 }
-
 
 // Input check behind bg_check_events: the smallest index of an event whose ordering is not a
 // permutation of 0..n-1 or whose helicity word has bits at or above n.
@@ -349,13 +462,15 @@ __global__ void k_check_final(int64_t* first_bad) {
 
 extern "C" {
 
-int bg_version(void) { return 10000; }
+int bg_version(void) { return 10100; }
+
+const char* bg_source_hash(void) { return BG_SOURCE_HASH; }
 
 const char* bg_strerror(int status) {
   switch (status) {
     case BG_OK: return "ok";
     case BG_EINVAL: return "invalid argument";
-    case BG_ENOTSUP: return "unsupported multiplicity or precision";
+    case BG_ENOTSUP: return "unsupported multiplicity, precision or lane form";
     case BG_EHIP: return "HIP runtime error";
     case BG_ENOMEM: return "device workspace allocation failed";
     default: return "unknown status";
@@ -387,6 +502,7 @@ int bg_set_lanes(int n, int prec, int lanes) {
   const Launchers* L = table(n, prec);
   if (!L) return BG_ENOTSUP;
   if (lanes != 0 && lanes != 1 && lanes != 2) return BG_EINVAL;
+  if (lanes == 1 && !(L->generate && L->amp2)) return BG_ENOTSUP;
   if (lanes == 2 && !(L->generate2 && L->amp2_2)) return BG_ENOTSUP;
   std::lock_guard<std::mutex> lk(g_shape_mu);
   g_lanes[n][prec == 32 ? 0 : 1] = lanes;
@@ -413,15 +529,17 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
                 const bg_outputs* outs, void* stream) {
   if (!cfgs || !counts || !outs || ncfg < 1 || ncfg > 16) return BG_EINVAL;
   GenClass G[16];
+  ClassPlan P[16];
   for (int k = 0; k < ncfg; ++k) {
-    const int st = fill_class(cfgs[k], counts[k], ins ? &ins[k] : nullptr, &outs[k], G[k]);
+    int st = fill_class(cfgs[k], counts[k], ins ? &ins[k] : nullptr, &outs[k], G[k]);
+    if (st == BG_OK) st = plan_class(cfgs[k], G[k], P[k]);
     if (st != BG_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
   // inverse-CDF tables of the classes that sample x1, x2
   for (int k = 0; k < ncfg; ++k) {
     if (!(G[k].use_pdf && !G[k].in_x && G[k].count > 0)) continue;
-    const int st = pdf_table(G[k].pdf, &G[k].pdf.tab);
+    const int st = pdf_table(G[k].pdf, &G[k].pdf.tab, s);
     if (st != BG_OK) return st;
   }
   const int mode = ncfg > 1 ? g_mixed_mode.load() : kSequential;
@@ -431,49 +549,56 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   if (mode == kPersistent) {
     std::vector<int> ks;
     for (int k = 0; k < ncfg; ++k)
-      if (cfgs[k].prec == 32 && G[k].count > 0) ks.push_back(k);
+      if (cfgs[k].prec == 32 && cfgs[k].polarisation == 0 && G[k].count > 0) ks.push_back(k);
     if (ks.size() > 1) {
-      const int st = generate_multi(cfgs, G, outs, ks, 32, s);
-      if (st != BG_OK) return st;
-      multi32 = true;
+      const int st = generate_multi(cfgs, G, outs, ks, s);
+      if (st != BG_OK && st != BG_ENOTSUP) return st;
+      multi32 = st == BG_OK;
     }
   }
   std::vector<int> todo;
   for (int k = 0; k < ncfg; ++k)
-    if (G[k].count > 0 && !(multi32 && cfgs[k].prec == 32)) todo.push_back(k);
+    if (G[k].count > 0 && !(multi32 && cfgs[k].prec == 32 && cfgs[k].polarisation == 0)) todo.push_back(k);
   if (todo.empty()) return BG_OK;
-  // per-class launch shapes and compensated-sum partials (allocated on the caller's stream
-  // before any fork, released on it after the join)
-  int block[16];
-  int64_t nblocks[16];
-  size_t off[16];
+  // compensated-sum partials and staging buffers, allocated on the caller's stream before
+  // any fork and released on it after the join
+  size_t off[16], soff[16];
+  int64_t scap[16];
   size_t bytes = 0;
-  int lanes[16];
   for (int k : todo) {
-    const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
-    lanes[k] = lanes_of(cfgs[k].n, cfgs[k].prec);
-    if (!(lanes[k] == 2 ? L->generate2 : L->generate)) return BG_ENOTSUP;
-    block[k] = (lanes[k] == 1 && lds_span_table(cfgs[k].n, cfgs[k].prec)) ? kLdsLanes
-                                                                           : shape_of(cfgs[k].n, cfgs[k].prec).block;
-    nblocks[k] = (lanes[k] * G[k].count + block[k] - 1) / block[k];
     off[k] = bytes;
-    if (outs[k].acc) bytes += ((size_t)nblocks[k] + kFinalizeGroups) * 4 * sizeof(double);
+    if (outs[k].acc) bytes += ((size_t)P[k].nblocks + kFinalizeGroups) * 4 * sizeof(double);
+    scap[k] = 0;
   }
-  Workspace parts{nullptr, s};
-  if (bytes > 0 && hipMallocAsync((void**)&parts.p, bytes, s) != hipSuccess) {
-    (void)hipGetLastError();
-    parts.p = nullptr;
-    return BG_ENOMEM;
+  const bool concurrent = mode == kConcurrent && todo.size() > 1;
+  // the split form's staging: one buffer per class when classes may run side by side,
+  // else one buffer reused by every class in turn
+  size_t shared_stage = 0;
+  for (int k : todo) {
+    if (!(P[k].lanes == 1 && split_form(cfgs[k].n, cfgs[k].prec))) continue;
+    scap[k] = std::min<int64_t>(kStageChunk, (G[k].count + kLdsLanes - 1) / kLdsLanes * kLdsLanes);
+    const size_t sb = (size_t)scap[k] * split_words(cfgs[k].n) * sizeof(double);
+    if (concurrent) {
+      soff[k] = bytes;
+      bytes += sb;
+    } else {
+      shared_stage = std::max(shared_stage, sb);
+    }
   }
+  if (!concurrent)
+    for (int k : todo) soff[k] = bytes;
+  bytes += shared_stage;
+  Workspace ws{nullptr, s};
+  if (int st = ws_alloc(&ws.p, bytes, s); st != BG_OK) return st;
   auto run_class = [&](int k, hipStream_t t) {
-    double* partials = outs[k].acc ? parts.p + off[k] / sizeof(double) : nullptr;
-    const Launchers* L = table(cfgs[k].n, cfgs[k].prec);
-    int st = from_hip((lanes[k] == 2 ? L->generate2 : L->generate)(G[k], partials, block[k], t));
-    if (st == BG_OK && partials)
-      st = from_hip(launch_finalize(partials, nblocks[k], partials + 4 * nblocks[k], outs[k].acc, t));
+    GenWork W{outs[k].acc ? ws.d() + off[k] / sizeof(double) : nullptr,
+              scap[k] > 0 ? ws.d() + soff[k] / sizeof(double) : nullptr, scap[k]};
+    int st = from_hip(P[k].fn(G[k], W, P[k].block, t));
+    if (st == BG_OK && W.partials)
+      st = from_hip(launch_finalize(W.partials, P[k].nblocks, W.partials + 4 * P[k].nblocks, outs[k].acc, t));
     return st;
   };
-  if (mode != kConcurrent || todo.size() < 2) {
+  if (!concurrent) {
     for (int k : todo) {
       const int st = run_class(k, s);
       if (st != BG_OK) return st;
@@ -521,13 +646,13 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
 int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, const uint8_t* order,
             double* amp2_out, void* stream) {
   const Launchers* L = table(n, prec);
-  if (!L || !L->amp2) return BG_ENOTSUP;
+  if (!L) return BG_ENOTSUP;
   if (N < 0) return BG_EINVAL;
+  const Amp2Fn f = lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2;
+  if (!f) return BG_ENOTSUP;
   if (N == 0) return BG_OK;
   if (!mom || !hel || !order || !amp2_out) return BG_EINVAL;
   const Shape sh = shape_of(n, prec);
-  const Amp2Fn f = lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2;
-  if (!f) return BG_ENOTSUP;
   return from_hip(f(N, mom, hel, order, amp2_out, sh.block, (hipStream_t)stream));
 }
 
@@ -549,10 +674,11 @@ int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const 
   const Launchers* L = table(cfg->n, cfg->prec);
   if (!L) return BG_ENOTSUP;
   if (N < 0) return BG_EINVAL;
+  if (!L->grad) return BG_ENOTSUP;
   if (N == 0) return BG_OK;
   if (!uniforms || !hel || !order || !grad_u || !grad_x || (cfg->use_pdf && !x12)) return BG_EINVAL;
   if (!(cfg->sqrt_s > 0) || !(cfg->alpha_s > 0) || (cfg->use_pdf != 0 && cfg->use_pdf != 1)) return BG_EINVAL;
-  if (!L->grad) return BG_ENOTSUP;
+  if (cfg->polarisation != 0) return BG_ENOTSUP;
   GradArgs G{};
   G.count = N;
   G.sqrt_s = cfg->sqrt_s;
@@ -571,12 +697,8 @@ int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const 
   hipStream_t s = (hipStream_t)stream;
   Workspace ws{nullptr, s};
   // the recursion's adjoints between the two gradient kernels: 12 (n - 1) + 1 words per event
-  if (hipMallocAsync((void**)&ws.p, (size_t)N * (12 * (cfg->n - 1) + 1) * sizeof(double), s) != hipSuccess) {
-    (void)hipGetLastError();
-    ws.p = nullptr;
-    return BG_ENOMEM;
-  }
-  G.pbuf = ws.p;
+  if (int st = ws_alloc(&ws.p, (size_t)N * (12 * (cfg->n - 1) + 1) * sizeof(double), s); st != BG_OK) return st;
+  G.pbuf = ws.d();
   const Shape sh = shape_of(cfg->n, cfg->prec);
   return from_hip(L->grad(G, sh.block, s));
 }

@@ -324,6 +324,8 @@ struct cv4 {
 // one ulp), in FP64 from correctly rounded square roots and divisions.
 template <typename T>
 __device__ __forceinline__ cv4<T> polarisation(const double p[4], bool plus) {
+  // no implicit fused multiply-adds: the vector rounds as written in every kernel
+#pragma clang fp contract(off)
   const T px = T(p[1]), py = T(p[2]), pz = T(p[3]);
   const T pt2 = px * px + py * py;
   T ct, st, cf = T(1), sf = T(0);
@@ -506,6 +508,9 @@ template <int L, int A, int B, typename T, typename KS>
 __device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Spans<L>::count],
                                             const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
                                             cv4<T>& V, T& sr, T& si) {
+  // every multiply-add below is an explicit fmac: the sum rounds identically wherever the
+  // recursion is inlined (the compiler contracts nothing on its own)
+#pragma clang fp contract(off)
   using SP = Spans<L>;
   cv4<T> X, Y;
 #pragma unroll
@@ -528,8 +533,8 @@ __device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Span
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
       const T dk = ka[mu] - kb[mu];
-      Y.re[mu] += dr * dk;
-      Y.im[mu] += di * dk;
+      Y.re[mu] = fmac(dr, dk, Y.re[mu]);
+      Y.im[mu] = fmac(di, dk, Y.im[mu]);
     }
     sr += dr;
     si += di;
@@ -557,8 +562,8 @@ __device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Span
   });
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    V.re[mu] = T(2) * X.re[mu] + Y.re[mu];
-    V.im[mu] = T(2) * X.im[mu] + Y.im[mu];
+    V.re[mu] = fmac(T(2), X.re[mu], Y.re[mu]);
+    V.im[mu] = fmac(T(2), X.im[mu], Y.im[mu]);
   }
 }
 
@@ -606,6 +611,145 @@ __device__ __forceinline__ void bg_amplitude(const KS& ks, const cv4<T> (&src)[L
   cdot(eps0, V, mr, mi);
   m_re = double(mr);
   m_im = double(mi);
+}
+
+// ----------------------------------------------------------------------------------------
+// Real currents (the paper's choice of sources, Sec. 3): every source is a real unit vector
+// orthogonal to its momentum, eps = cos(psi) e1 + sin(psi) e2 with the transverse basis
+// e1 = (0, cos t cos f, cos t sin f, -sin t), e2 = (0, -sin f, cos f, 0) of the physical
+// momentum (the helicity vectors above are (-h e1 - i e2)/sqrt 2), psi uniform.  Then every
+// current is real: the same brackets and closure as above with real four-vectors, a
+// quarter of the multiplications and half of the storage.  2^n |A(eps)|^2 averages over
+// the angles to the helicity sum.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+struct rv4 {
+  T v[4];
+};
+
+// (cos psi, sin psi) as (c, s); no implicit fused multiply-adds, as polarisation()
+template <typename T>
+__device__ __forceinline__ rv4<T> real_polarisation(const double p[4], T c, T s) {
+#pragma clang fp contract(off)
+  const T px = T(p[1]), py = T(p[2]), pz = T(p[3]);
+  const T pt2 = px * px + py * py;
+  T ct, st, cf = T(1), sf = T(0);
+  if constexpr (std::is_same<T, float>::value) {
+    const float ipa = __builtin_amdgcn_rsqf(pt2 + pz * pz);
+    const float ipt = __builtin_amdgcn_rsqf(pt2);
+    ct = pz * ipa;
+    st = pt2 > 0.0f ? (pt2 * ipt) * ipa : 0.0f;
+    if (pt2 > 0.0f) {
+      cf = px * ipt;
+      sf = py * ipt;
+    }
+  } else {
+    const T pa = sqrt(pt2 + pz * pz);
+    const T pt = sqrt(pt2);
+    const T ipa = T(1) / pa;
+    ct = pz * ipa;
+    st = pt * ipa;
+    if (pt2 > T(0)) {
+      const T ipt = T(1) / pt;
+      cf = px * ipt;
+      sf = py * ipt;
+    }
+  }
+  rv4<T> e;
+  e.v[0] = T(0);
+  e.v[1] = fmac(c * ct, cf, -(s * sf));
+  e.v[2] = fmac(c * ct, sf, s * cf);
+  e.v[3] = -(c * st);
+  return e;
+}
+
+// x . y (metric (+,-,-,-)) of real four-vectors
+template <typename T>
+__device__ __forceinline__ T vdot(const rv4<T>& x, const T (&y)[4]) {
+  T r = x.v[0] * y[0];
+  r = fmac(-x.v[1], y[1], r);
+  r = fmac(-x.v[2], y[2], r);
+  return fmac(-x.v[3], y[3], r);
+}
+
+template <typename T>
+__device__ __forceinline__ T vdot(const rv4<T>& x, const rv4<T>& y) {
+  return vdot(x, y.v);
+}
+
+// acc += c y
+template <typename T>
+__device__ __forceinline__ void vaxpy(T c, const rv4<T>& y, rv4<T>& acc) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) acc.v[mu] = fmac(c, y.v[mu], acc.v[mu]);
+}
+
+// One span [A..B] with real currents: its bracket sum V (regrouped as span_vertex).
+template <int L, int A, int B, typename T, typename KS>
+__device__ __forceinline__ void span_vertex_r(const KS& ks, const rv4<T> (&J)[Spans<L>::count],
+                                              const T (&S)[Spans<L>::count], rv4<T>& V, T& sv) {
+#pragma clang fp contract(off)
+  using SP = Spans<L>;
+  rv4<T> X, Y;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) X.v[mu] = Y.v[mu] = T(0);
+  sv = T(0);
+  static_for<A, B>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int PA = SP::at(A, i), PB = SP::at(i + 1, B);
+    T ka[4], kb[4];
+    ks.template K<A, i>(ka);
+    ks.template K<i + 1, B>(kb);
+    const T d = vdot(J[PA], J[PB]);
+    vaxpy(vdot(J[PA], kb), J[PB], X);
+    vaxpy(-vdot(J[PB], ka), J[PA], X);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) Y.v[mu] = fmac(d, ka[mu] - kb[mu], Y.v[mu]);
+    sv += d;
+  });
+  static_for<A, B - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    static_for<i + 1, B>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      vaxpy(vdot(J[SP::at(A, i)], J[SP::at(j + 1, B)]), J[SP::at(i + 1, j)], X);
+    });
+  });
+  static_for<A + 1, B>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    vaxpy(-S[SP::at(A, j)], J[SP::at(j + 1, B)], Y);
+  });
+  static_for<A, B - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    vaxpy(-S[SP::at(i + 1, B)], J[SP::at(A, i)], Y);
+  });
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) V.v[mu] = fmac(T(2), X.v[mu], Y.v[mu]);
+}
+
+// Real recursion and closure m = eps0 . V[0..L-1].
+template <int L, typename T, typename KS>
+__device__ __forceinline__ double bg_amplitude_r(const KS& ks, const rv4<T> (&src)[L], const rv4<T>& eps0) {
+  using SP = Spans<L>;
+  rv4<T> J[SP::count];
+  T S[SP::count];
+  static_for<0, L>([&](auto ac) { J[decltype(ac)::value] = src[decltype(ac)::value]; });
+  static_for<2, L>([&](auto lc) {
+    constexpr int len = decltype(lc)::value;
+    static_for<0, L - len + 1>([&](auto ac) {
+      constexpr int a = decltype(ac)::value, b = a + len - 1, s = SP::at(a, b);
+      rv4<T> V;
+      T sv;
+      span_vertex_r<L, a, b, T>(ks, J, S, V, sv);
+      const T prop = ks.template prop<a, b>();
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) J[s].v[mu] = V.v[mu] * prop;
+      S[s] = sv;
+    });
+  });
+  rv4<T> V;
+  T sv;
+  span_vertex_r<L, 0, L - 1, T>(ks, J, S, V, sv);
+  return double(vdot(eps0, V));
 }
 
 // ----------------------------------------------------------------------------------------

@@ -1,18 +1,17 @@
-// Instantiates one kernel kind (BG_KIND: 0 generate, 1 amp2, 2 gradient) of one
-// multiplicity (BG_N, 4..12) and recursion precision (BG_PREC, 32 or 64), and exports its
-// launcher through a host function resolved by the C-ABI layer.
+// Instantiates one kernel of the library and exports its launcher through a host function
+// resolved by the C-ABI layer:
+//   BG_KIND 0 generate, 1 amp2, 2 gradient;  BG_N 4..12;  BG_PREC 32 or 64;
+//   BG_FORM 1 one event per lane (for generation of the table classes: the split form),
+//           2 two lanes per event (kinds 0 and 1 only),
+//           3 one event per lane with real polarisations (kind 0 only).
+// One kernel per translation unit keeps every unit small enough to compile in parallel.
 #include "bg_adjoint.hpp"
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
-#if BG_KIND == 0 && BG_PREC == 32 && BG_N <= 8
 #include "bg_split.hpp"
-#define BG_SPLIT 1
-#else
-#define BG_SPLIT 0
-#endif
 
-#if !defined(BG_N) || !defined(BG_PREC) || !defined(BG_KIND)
-#error "BG_N, BG_PREC and BG_KIND must be defined"
+#if !defined(BG_N) || !defined(BG_PREC) || !defined(BG_KIND) || !defined(BG_FORM)
+#error "BG_N, BG_PREC, BG_KIND and BG_FORM must be defined"
 #endif
 
 #define BG_CAT4(a, b, c, d) a##b##_p##c##_k##d
@@ -26,43 +25,48 @@ using Real = float;
 using Real = double;
 #endif
 
-// the two-lane forms, for the multiplicities of has_lane_pairs
-#if (BG_PREC == 32 && BG_N >= 9) || (BG_PREC == 64 && BG_N >= 6)
-#define BG_PAIRS 1
-#else
-#define BG_PAIRS 0
-#endif
-static_assert(has_lane_pairs(BG_N, BG_PREC) == (BG_PAIRS == 1), "lane-pair build condition");
+static_assert(BG_KIND == 2 || (BG_FORM == 1 && has_one_lane(BG_N, BG_PREC)) ||
+                  (BG_FORM == 2 && has_lane_pairs(BG_N, BG_PREC)) || (BG_FORM == 3 && has_real_pol(BG_N, BG_PREC)),
+              "this lane form is not built for (n, prec)");
 
 // Launchers take the workgroup size chosen by the host (which also sizes the partials:
-// one per workgroup, ceil(count * lanes / block) workgroups).
-#if BG_KIND == 0
-hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
+// one per workgroup, ceil(count * lanes / block) workgroups; the table classes always use
+// one partial per kLdsLanes events).
+#if BG_KIND == 0 && BG_FORM == 1
+hipError_t BG_NAME(launch_generate_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
                                                               hipStream_t s) {
-  const bool table = lds_span_table(BG_N, BG_PREC);
-  if (table) block = kLdsLanes;
-#if BG_SPLIT
-  // kinematics and recursion as two kernels for large calls; the fused kernel for small
-  // ones and if there is no staging memory
-  if (C.count >= kSplitMinEvents) {
-    const hipError_t e = launch_generate_split<BG_N, Real>(C, partials, s);
-    if (e != hipErrorOutOfMemory) return e;
-  }
-#endif
+#if BG_PREC == 32 && BG_N <= 8
+  (void)block;
+  static_assert(split_form(BG_N, BG_PREC), "split-form classes");
+  return launch_generate_split<BG_N>(C, W, s);
+#else
   const int64_t nb = (C.count + block - 1) / block;
-  hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), table ? 0 : perm_lds_bytes(BG_N, block),
-                     s, C, partials);
+  hipLaunchKernelGGL((k_generate<BG_N, Real>), dim3((unsigned)nb), dim3(block), perm_lds_bytes(BG_N, block), s, C,
+                     W.partials);
   return hipGetLastError();
+#endif
 }
-#if BG_PAIRS
-hipError_t BG_NAME(launch_generate2_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, double* partials, int block,
+#elif BG_KIND == 0 && BG_FORM == 3
+hipError_t BG_NAME(launch_generate_real_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
+                                                                   hipStream_t s) {
+#if BG_PREC == 32 && BG_N <= 8
+  (void)block;
+  return launch_generate_split<BG_N, 1>(C, W, s);
+#else
+  const int64_t nb = (C.count + block - 1) / block;
+  hipLaunchKernelGGL((k_generate<BG_N, Real, 1>), dim3((unsigned)nb), dim3(block), perm_lds_bytes(BG_N, block), s,
+                     C, W.partials);
+  return hipGetLastError();
+#endif
+}
+#elif BG_KIND == 0 && BG_FORM == 2
+hipError_t BG_NAME(launch_generate2_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
                                                                hipStream_t s) {
   const int64_t nb = (2 * C.count + block - 1) / block;
-  hipLaunchKernelGGL((k_generate_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, C, partials);
+  hipLaunchKernelGGL((k_generate_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, C, W.partials);
   return hipGetLastError();
 }
-#endif
-#elif BG_KIND == 1
+#elif BG_KIND == 1 && BG_FORM == 1
 hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
                                                           const uint8_t* order, double* out, int block,
                                                           hipStream_t s) {
@@ -71,7 +75,7 @@ hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const d
   hipLaunchKernelGGL((k_amp2<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
   return hipGetLastError();
 }
-#if BG_PAIRS
+#elif BG_KIND == 1 && BG_FORM == 2
 hipError_t BG_NAME(launch_amp2_2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
                                                             const uint8_t* order, double* out, int block,
                                                             hipStream_t s) {
@@ -79,7 +83,6 @@ hipError_t BG_NAME(launch_amp2_2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const
   hipLaunchKernelGGL((k_amp2_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
   return hipGetLastError();
 }
-#endif
 #elif BG_KIND == 2
 // Two kernels: the recursion and its reverse sweep (one or two lanes per event), then the
 // helicity-source, momentum, RAMBO and x adjoints (one lane per event).
@@ -101,6 +104,8 @@ hipError_t BG_NAME(launch_grad_n, BG_N, BG_PREC, BG_KIND)(const GradArgs& G, int
   hipLaunchKernelGGL((k_grad_back<BG_N>), dim3((unsigned)((G.count + 255) / 256)), dim3(256), 0, s, G);
   return hipGetLastError();
 }
+#else
+#error "unknown kernel kind or form"
 #endif
 
 }  // namespace bgk

@@ -433,7 +433,71 @@ __device__ __forceinline__ double ordered_amp2(const double (&p)[N][4], const ui
     SpanKLegs<N - 1, T> ks{k};
     bg_amplitude<N - 1, T>(ks, src, e0, mr, mi);
   }
-  return ldexp(mr * mr + mi * mi, 2 * ex * (4 - N) - (N - 2));
+  return ldexp(__builtin_fma(mr, mr, mi * mi), 2 * ex * (4 - N) - (N - 2));
+}
+
+// Angles of the real polarisations of an event (random_polarisation): leg k takes word k % 4
+// of Philox block n_blocks + k / 4 (after the draws of the helicity mode), psi = 2 pi u;
+// returns cos psi, sin psi per leg, evaluated in FP64.
+template <int N>
+__device__ __forceinline__ void polarisation_angles(const GenClass& C, int64_t i, double (&cs)[N][2]) {
+  const uint64_t e = C.first_event + (uint64_t)i;
+  const EventRng rng{(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)N, C.key0, C.key1};
+  constexpr uint32_t b0 = 1u + (N - 2) + (N - 2 + 3) / 4;
+  u32x4 w{};
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if ((k & 3) == 0) w = rng.block(b0 + (uint32_t)(k / 4));
+    sincospi_fp64(2.0 * u01(w.v[k & 3]), &cs[k][1], &cs[k][0]);
+  }
+}
+
+// |A(sigma; eps_psi)|^2 with real polarisations (cs: cos, sin of each leg's angle), as
+// ordered_amp2.
+template <int N, typename T, bool LDS>
+__device__ __forceinline__ double ordered_amp2_real(const double (&p)[N][4], const uint32_t (&leg)[N],
+                                                    const double (&cs)[N][2], LdsTable<N>* tab) {
+  double esum = 0.0;
+#pragma unroll
+  for (int t = 0; t < N; ++t) esum += fabs(p[t][0]);
+  const int ex = ilogb(0.5 * esum);
+  const double sc = ldexp(1.0, -ex);
+  double k[N - 1][4];
+  rv4<T> src[N - 1];
+  // the angle of the leg at each position, selected without dynamic register indexing
+  auto angle = [&](uint32_t l, T& c, T& s) {
+    double cd = cs[0][0], sd = cs[0][1];
+#pragma unroll
+    for (int q = 1; q < N; ++q) {
+      cd = l == (uint32_t)q ? cs[q][0] : cd;
+      sd = l == (uint32_t)q ? cs[q][1] : sd;
+    }
+    c = T(cd);
+    s = T(sd);
+  };
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    const double sg = leg[t] < 2u ? -sc : sc;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) k[t - 1][mu] = sg * p[t][mu];
+    T c, s;
+    angle(leg[t], c, s);
+    src[t - 1] = real_polarisation<T>(p[t], c, s);
+  }
+  T c0, s0;
+  angle(leg[0], c0, s0);
+  const rv4<T> e0 = real_polarisation<T>(p[0], c0, s0);
+  double m;
+  if constexpr (LDS) {
+    __syncthreads();
+    SpanKLds<N - 1, kLdsLanes> ks{tab->k + threadIdx.x, tab->p + threadIdx.x};
+    ks.fill(k);
+    m = bg_amplitude_r<N - 1, T>(ks, src, e0);
+  } else {
+    SpanKLegs<N - 1, T> ks{k};
+    m = bg_amplitude_r<N - 1, T>(ks, src, e0);
+  }
+  return ldexp(m * m, 2 * ex * (4 - N) - (N - 2));
 }
 
 // The same with the event spread over the G lanes of a group; g is this lane's place in it.
@@ -473,7 +537,7 @@ __device__ __forceinline__ double ordered_amp2_g(const double (&p)[N][4], const 
   SpanKGroup<N - 1, G, T> ks{k, lsd.sg};
   double mr, mi;
   bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
-  return ldexp(mr * mr + mi * mi, 2 * ex * (4 - N) - (N - 2));
+  return ldexp(__builtin_fma(mr, mr, mi * mi), 2 * ex * (4 - N) - (N - 2));
 }
 
 // Compensated (sum w, sum w^2) of a workgroup of up to 256 lanes, in a fixed tree order;
@@ -503,13 +567,37 @@ __device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst)
   }
 }
 
+// The weight of Eq. 3.8 from |A|^2 (w = 0 exactly when the event fails the cuts, never
+// 0 times a product), and the per-event outputs of |A|^2, the weight, the cut flag and the
+// log integrand weight; returns w.  Shared by every generation kernel, so that each
+// output rounds identically whichever kernel evaluates the event.
+template <int N>
+__device__ __forceinline__ double finish_event(const GenClass& C, int64_t i, bool pass, double a2, double shat,
+                                               double x1, double x2) {
+#pragma clang fp contract(off)
+  double sp = 1.0;
+#pragma unroll
+  for (int k = 0; k < (N > 5 ? N - 5 : 5 - N); ++k) sp *= shat;
+  if (N < 5) sp = 1.0 / sp;
+  const double w = pass ? C.wconst * sp * a2 : 0.0;
+  if (C.out.weight) C.out.weight[i] = w;
+  if (C.out.amp2) C.out.amp2[i] = a2;
+  if (C.out.pass) C.out.pass[i] = pass ? 1 : 0;
+  if (C.out.logw) {
+    double lw = log(a2) + double(N - 5) * log(shat) + C.log_const;
+    if (C.use_pdf) lw += C.pdf.a * (log(x1) + log(x2)) + double(C.pdf.b) * (log1p(-x1) + log1p(-x2));
+    C.out.logw[i] = a2 > 0.0 ? lw : -INFINITY;
+  }
+  return w;
+}
+
 // One event: draws -> kinematics -> cuts -> |A|^2 -> weight; writes outputs; returns w.
 // With G > 1 lanes per event every lane of the group evaluates the kinematics (the same
 // values), the recursion is shared, and lane g = 0 writes the outputs and returns w
-// (the others return 0).
-template <int N, typename T, bool LDS = false, int G = 1>
-__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, PermLds perm, LdsTable<N>* tab = nullptr,
-                                               int g = 0) {
+// (the others return 0).  Not used for the table classes, which run split (bg_split.hpp).
+template <int N, typename T, int G = 1, int POL = 0>
+__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, PermLds perm, int g = 0) {
+  static_assert(POL == 0 || G == 1, "real polarisations run one lane per event");
   using Kin = typename std::conditional<G == 1, EventKin<N>, EventKinPos<N>>::type;
   Kin ev;
   double ht, rmin;
@@ -524,50 +612,34 @@ __device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, Per
   }
   // |A|^2 is Lorentz invariant: evaluated in the partonic centre-of-mass frame
   double a2;
-  if constexpr (G == 1)
-    a2 = ordered_amp2<N, T, LDS>(ev.pc, ev.leg, ev.hel, tab);
-  else
+  if constexpr (POL == 1) {
+    double cs[N][2];
+    polarisation_angles<N>(C, i, cs);
+    a2 = ordered_amp2_real<N, T, false>(ev.pc, ev.leg, cs, nullptr);
+  } else if constexpr (G == 1) {
+    a2 = ordered_amp2<N, T, false>(ev.pc, ev.leg, ev.hel, nullptr);
+  } else {
     a2 = ordered_amp2_g<N, T, G>(ev.pc, ev.leg, ev.hel, g);
+  }
   if (g != 0) return 0.0;
-  double sp = 1.0;
-#pragma unroll
-  for (int k = 0; k < (N > 5 ? N - 5 : 5 - N); ++k) sp *= ev.shat;
-  if (N < 5) sp = 1.0 / sp;
-  const double w = pass ? C.wconst * sp * a2 : 0.0;
-  if (C.out.weight) C.out.weight[i] = w;
-  if (C.out.amp2) C.out.amp2[i] = a2;
-  if (C.out.pass) C.out.pass[i] = pass ? 1 : 0;
   if (C.out.obs) {
     C.out.obs[2 * i] = ht;
     C.out.obs[2 * i + 1] = rmin;
   }
-  if (C.out.logw) {
-    double lw = log(a2) + (N - 5) * log(ev.shat) + C.log_const;
-    if (C.use_pdf) lw += C.pdf.a * (log(ev.x1) + log(ev.x2)) + C.pdf.b * (log1p(-ev.x1) + log1p(-ev.x2));
-    C.out.logw[i] = a2 > 0.0 ? lw : -INFINITY;
-  }
-  return w;
+  return finish_event<N>(C, i, pass, a2, ev.shat, ev.x1, ev.x2);
 }
 
-// Single-class generation: one event per lane, one compensated partial per workgroup.
-// Launch: one event per lane, blockDim.x = kLdsLanes where UseLdsK holds (no dynamic LDS),
-// else any of {64, 128, 192, 256} with perm_lds_bytes(N, blockDim.x) bytes of dynamic LDS;
-// partials may be NULL.
-template <int N, typename T>
-__global__ __launch_bounds__((UseLdsK<N, T>::value ? kLdsLanes : 256)) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate(
-    GenClass C, double* partials) {
+// Single-class generation of a class without the span table (FP32 n = 9, FP64 n <= 6): one
+// event per lane, one compensated partial per workgroup.  Launch: blockDim.x in
+// {64, 128, 192, 256} with perm_lds_bytes(N, blockDim.x) bytes of dynamic LDS; partials may
+// be NULL.
+template <int N, typename T, int POL = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate(GenClass C,
+                                                                                            double* partials) {
+  static_assert(!UseLdsK<N, T>::value, "the table classes generate in the split form");
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double w = 0.0;
-  if constexpr (UseLdsK<N, T>::value) {
-    // the span table's memory first carries the momentum permutation (one wave per
-    // workgroup: every lane has read its momenta before any lane fills the table)
-    __shared__ LdsTable<N> tab;
-    static_assert(sizeof(LdsTable<N>) >= sizeof(double) * 4 * (N - 2) * kLdsLanes, "permutation fits the table");
-    const PermLds perm{reinterpret_cast<double*>(&tab) + threadIdx.x, kLdsLanes};
-    if (i < C.count) w = generate_one<N, T, true>(C, i, perm, &tab);
-  } else {
-    if (i < C.count) w = generate_one<N, T>(C, i, dyn_perm());
-  }
+  if (i < C.count) w = generate_one<N, T, 1, POL>(C, i, dyn_perm());
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
 }
 
@@ -605,7 +677,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int g = (int)(threadIdx.x % G);
   double w = 0.0;
-  if (i < C.count) w = generate_one<N, T, false, G>(C, i, PermLds{nullptr, 0}, nullptr, g);
+  if (i < C.count) w = generate_one<N, T, G>(C, i, PermLds{nullptr, 0}, g);
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
 }
 

@@ -19,11 +19,22 @@ constexpr int kLdsLanes = 64;
 constexpr unsigned perm_lds_bytes(int n, int block) { return 8u * 4u * (unsigned)(n - 2) * (unsigned)block; }
 constexpr bool lds_span_table(int n, int prec) { return prec == 32 && n <= 8; }
 
-// Multiplicities whose kernels are also built with an event spread over two lanes (the
-// one-lane recursion needs more than 512 registers there); which form runs is a launch
-// setting (bg_set_lanes), defaulting to default_lanes.
+// The table classes generate events in two kernels (kinematics at several waves per SIMD,
+// then the recursion at one), joined by a staging buffer of split_words(n) doubles per event.
+constexpr bool split_form(int n, int prec) { return lds_span_table(n, prec); }
+constexpr int split_words(int n) { return 4 * n + 5; }
+
+// Lane forms the library holds per (n, prec): one event per lane where the recursion fits a
+// lane's 512 registers (FP32 n <= 9, FP64 n <= 6), two lanes per event from FP32 n = 9 and
+// FP64 n = 6 on (the one-lane form spills kilobytes per lane beyond that).  Which form runs
+// is a launch setting (bg_set_lanes), defaulting to default_lanes.
+constexpr bool has_one_lane(int n, int prec) { return prec == 32 ? n <= 9 : n <= 6; }
 constexpr bool has_lane_pairs(int n, int prec) { return prec == 32 ? n >= 9 : n >= 6; }
 constexpr int default_lanes(int n, int prec) { return prec == 32 ? (n >= 10 ? 2 : 1) : (n >= 7 ? 2 : 1); }
+
+// Classes built with real polarisations (real currents: half the registers of complex ones,
+// so one lane per event fits every FP32 class).
+constexpr bool has_real_pol(int n, int prec) { return prec == 32 ? n <= 12 : n <= 8; }
 
 // The gradient kernel with an event on two lanes (forward values staged in LDS, which
 // bounds it to FP32 n <= 8); elsewhere one lane per event.
@@ -47,17 +58,26 @@ struct GradArgs {
   double* pbuf;      // workspace [12 (n - 1) + 1][count]: recursion adjoints between the two kernels
 };
 
-using GenerateFn = hipError_t (*)(const GenClass& C, double* partials, int block, hipStream_t s);
+// Device memory a generation launch works in: per-workgroup partials (NULL: no totals) and,
+// for the split form, a staging buffer of stage_cap events.
+struct GenWork {
+  double* partials;
+  double* stage;
+  int64_t stage_cap;
+};
+
+using GenerateFn = hipError_t (*)(const GenClass& C, const GenWork& W, int block, hipStream_t s);
 using Amp2Fn = hipError_t (*)(int64_t count, const double* mom, const uint32_t* hel, const uint8_t* order,
                               double* out, int block, hipStream_t s);
 using GradFn = hipError_t (*)(const GradArgs& G, int block, hipStream_t s);
 
 struct Launchers {
-  GenerateFn generate;
+  GenerateFn generate;   // one lane per event (the split form for the table classes)
   Amp2Fn amp2;
   GradFn grad;
   GenerateFn generate2;  // two lanes per event (where has_lane_pairs)
   Amp2Fn amp2_2;
+  GenerateFn generate_real;  // real polarisations, one lane per event (where has_real_pol)
 };
 
 // Fixed-order compensated reduction of nparts partials into acc, through level2
@@ -67,10 +87,16 @@ constexpr int kFinalizeGroups = 512;
 hipError_t launch_finalize(const double* partials, int64_t nparts, double* level2, double* acc, hipStream_t s);
 
 // One class of a multi-class launch and one tile of its work list (device-resident).
+// Table classes (n <= 8) are staged: their kinematics run in the multi-class kinematics
+// kernel (workgroups kin_begin .. of it), their stage is at stage + stage_off; the others
+// are generated two lanes per event inside the persistent kernel.
 struct MultiClass {
   GenClass C;
   int32_t n;
   int32_t tile_begin, tile_end;  // this class's tiles in the list
+  int32_t staged;
+  int64_t kin_begin;             // first kinematics workgroup (staged classes)
+  int64_t stage_off;             // offset of the class's stage, in doubles
   double* acc;
 };
 
@@ -80,7 +106,11 @@ struct Tile {
   int32_t cls;
 };
 
-hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
-                                     int* counter, double* partials, int grid, int block, hipStream_t s);
+constexpr int kKinBlock = 128;   // workgroup of the kinematics kernels
+constexpr int kMultiBlock = 64;  // workgroup (one wave) of the persistent kernel
+
+hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, int nstaged, int64_t kin_blocks,
+                                     const Tile* tiles, int ntiles, int* counter, double* stage, double* partials,
+                                     int grid, hipStream_t s);
 
 }  // namespace bgk

@@ -1,58 +1,98 @@
-// Multi-class generation in one persistent launch (mixed multiplicities n = 4..12).
+// Multi-class generation (mixed multiplicities n = 4..12, FP32 recursion) in one persistent
+// launch.
 //
-// The host builds a tile list (class, first event, count), ordered by decreasing n so the
-// most expensive tiles start first, with each class's tiles contiguous.  Every workgroup
-// takes tiles from a global counter until the list is exhausted (every wave reaches that
-// exit), evaluates each event with the same per-multiplicity code as the single-class
-// kernel, and writes one compensated (sum w, sum w^2) partial per tile.  A second kernel
-// reduces each class's tile partials in tile order into that class's accumulator, so
-// per-event outputs and totals do not depend on which workgroup ran which tile.
-//
-// Built for FP32 recursion (the mixed-multiplicity workload); FP64 classes of a
-// multi-class call are launched one class at a time by the host layer.
+// The table classes (n <= 8) first run their kinematics in one multi-class kernel at several
+// waves per SIMD (the same per-event body as the single-class k_kin), which stages every
+// event of those classes.  Then one persistent kernel of one-wave workgroups takes tiles
+// from a shared queue ordered by decreasing n, so that the expensive large-n tiles start
+// first and the cheap staged tiles fill in behind them: a tile of a class with n >= 9 is
+// generated start to finish with two lanes per event (the single-class two-lane body), a
+// tile of a staged class is finished with one lane per event and the LDS span table (the
+// single-class k_rec body).  Every wave reaches the queue's end, where the loop exits.  One
+// compensated partial per tile; a last kernel reduces each class's partials in tile order.
+// Per-event values are therefore bitwise those of the single-class launches.
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
+#include "bg_split.hpp"
 
 namespace bgk {
 
-using Real = float;
-
 namespace {
 
-template <typename T>
-__device__ __forceinline__ double generate_any(int n, const GenClass& C, int64_t e, PermLds perm) {
-  switch (n) {
-    case 4: return generate_one<4, T>(C, e, perm);
-    case 5: return generate_one<5, T>(C, e, perm);
-    case 6: return generate_one<6, T>(C, e, perm);
-    case 7: return generate_one<7, T>(C, e, perm);
-    case 8: return generate_one<8, T>(C, e, perm);
-    case 9: return generate_one<9, T>(C, e, perm);
-    case 10: return generate_one<10, T>(C, e, perm);
-    case 11: return generate_one<11, T>(C, e, perm);
-    default: return generate_one<12, T>(C, e, perm);
+// the class of kinematics workgroup b (staged classes hold consecutive workgroup ranges)
+__device__ __forceinline__ int kin_class(const MultiClass* __restrict__ classes, int nstaged, int64_t b) {
+  int c = 0;
+  for (int k = 1; k < nstaged; ++k) c = b >= classes[k].kin_begin ? k : c;
+  return c;
+}
+
+// Launch: kKinBlock threads, perm_lds_bytes(8, kKinBlock) bytes of dynamic LDS, one
+// workgroup per kKinBlock events of each staged class; classes[0 .. nstaged-1] are the
+// staged ones, in workgroup order.
+__global__ __launch_bounds__(kKinBlock) void k_kin_multi(const MultiClass* __restrict__ classes, int nstaged,
+                                                         double* __restrict__ stage) {
+  const int c = __builtin_amdgcn_readfirstlane(kin_class(classes, nstaged, blockIdx.x));
+  const MultiClass& mc = classes[c];
+  const int64_t j = ((int64_t)blockIdx.x - mc.kin_begin) * kKinBlock + threadIdx.x;
+  if (j >= mc.C.count) return;
+  double* buf = stage + mc.stage_off;
+  switch (mc.n) {
+    case 4: kin_one<4>(mc.C, j, j, buf, dyn_perm()); break;
+    case 5: kin_one<5>(mc.C, j, j, buf, dyn_perm()); break;
+    case 6: kin_one<6>(mc.C, j, j, buf, dyn_perm()); break;
+    case 7: kin_one<7>(mc.C, j, j, buf, dyn_perm()); break;
+    default: kin_one<8>(mc.C, j, j, buf, dyn_perm()); break;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate_multi(
+// The per-class tile bodies are separate functions (not inlined into the kernel): each is
+// register-allocated on its own, which keeps the kernel's compile time near the sum of the
+// single-class kernels' instead of growing with the square of the whole body.
+template <int N>
+__device__ __attribute__((noinline)) void staged_tile(const MultiClass& mc, const Tile& tl, const double* __restrict__ stage,
+                                            void* lds, CSum& w, CSum& w2) {
+  const double* buf = stage + mc.stage_off;  // slot = the class's local event index
+  for (int64_t i = tl.first + threadIdx.x; i < tl.first + tl.count; i += kMultiBlock) {
+    const double x = rec_one<N>(mc.C, i, i, buf, reinterpret_cast<LdsTable<N>*>(lds));
+    w = cs_add(w, CSum{x, 0.0});
+    w2 = cs_add(w2, CSum{x * x, 0.0});
+  }
+}
+
+template <int N>
+__device__ __attribute__((noinline)) void paired_tile(const MultiClass& mc, const Tile& tl, CSum& w, CSum& w2) {
+  const int g = (int)(threadIdx.x & 1u);
+  for (int64_t i = tl.first + (threadIdx.x >> 1); i < tl.first + tl.count; i += kMultiBlock / 2) {
+    const double x = generate_one<N, float, 2>(mc.C, i, PermLds{nullptr, 0}, g);
+    w = cs_add(w, CSum{x, 0.0});
+    w2 = cs_add(w2, CSum{x * x, 0.0});
+  }
+}
+
+__global__ __launch_bounds__(kMultiBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate_multi(
     const MultiClass* __restrict__ classes, const Tile* __restrict__ tiles, int ntiles, int* counter,
-    double* partials) {
+    const double* __restrict__ stage, double* partials) {
+  __shared__ LdsTable<8> lds;  // the span table of the staged classes (n <= 8 fits n = 8's)
   __shared__ int s_tile;
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
     __syncthreads();
-    // uniform across the workgroup: class parameters are read with scalar loads
     const int t = __builtin_amdgcn_readfirstlane(s_tile);
     __syncthreads();
     if (t >= ntiles) break;
     const Tile tl = tiles[t];
     const MultiClass& mc = classes[tl.cls];
     CSum w{0.0, 0.0}, w2{0.0, 0.0};
-    for (int64_t i = tl.first + threadIdx.x; i < tl.first + tl.count; i += blockDim.x) {
-      const double x = generate_any<T>(mc.n, mc.C, i, dyn_perm());
-      w = cs_add(w, CSum{x, 0.0});
-      w2 = cs_add(w2, CSum{x * x, 0.0});
+    switch (mc.n) {
+      case 4: staged_tile<4>(mc, tl, stage, &lds, w, w2); break;
+      case 5: staged_tile<5>(mc, tl, stage, &lds, w, w2); break;
+      case 6: staged_tile<6>(mc, tl, stage, &lds, w, w2); break;
+      case 7: staged_tile<7>(mc, tl, stage, &lds, w, w2); break;
+      case 8: staged_tile<8>(mc, tl, stage, &lds, w, w2); break;
+      case 9: paired_tile<9>(mc, tl, w, w2); break;
+      case 10: paired_tile<10>(mc, tl, w, w2); break;
+      case 11: paired_tile<11>(mc, tl, w, w2); break;
+      default: paired_tile<12>(mc, tl, w, w2); break;
     }
     block_reduce_store(w, w2, partials + 4 * (int64_t)t);
     __syncthreads();
@@ -95,11 +135,16 @@ __global__ __launch_bounds__(256) void k_finalize_multi(const MultiClass* __rest
 
 }  // namespace
 
-hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, const Tile* tiles, int ntiles,
-                                  int* counter, double* partials, int grid, int block, hipStream_t s) {
-  // dynamic LDS: the momentum permutation column of the largest multiplicity
-  hipLaunchKernelGGL((k_generate_multi<Real>), dim3(grid), dim3(block), perm_lds_bytes(12, block), s, classes, tiles,
-                     ntiles, counter,
+hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, int nstaged, int64_t kin_blocks,
+                                     const Tile* tiles, int ntiles, int* counter, double* stage, double* partials,
+                                     int grid, hipStream_t s) {
+  if (nstaged > 0 && kin_blocks > 0) {
+    hipLaunchKernelGGL(k_kin_multi, dim3((unsigned)kin_blocks), dim3(kKinBlock), perm_lds_bytes(8, kKinBlock), s,
+                       classes, nstaged, stage);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_generate_multi, dim3(grid), dim3(kMultiBlock), 0, s, classes, tiles, ntiles, counter, stage,
                      partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -27,6 +27,7 @@ struct GenClass {
   uint64_t first_event;
   uint32_t key0, key1;
   int32_t use_pdf, random_order;
+  int32_t polarisation;       // 0 helicity states, 1 random real unit vectors
   double sqrt_s;              // collider sqrt(S), or the fixed sqrt(s_hat) without PDF
   double pt_min, eta_max, dr_min;
   double wconst;              // event-independent weight factor (pb GeV^(2(5-n)))

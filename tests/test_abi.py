@@ -44,7 +44,7 @@ def test_host_error_paths():
     c = bg.config(8, prec=16)
     assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_ENOTSUP
     c = bg.config(8)
-    c.reserved = 1
+    c.polarisation = 2
     assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_EINVAL
     c = bg.config(8, pt_min=0.0)            # tau_min would be 0: the density is not integrable
     assert lib.bg_generate(ctypes.byref(c), 1, counts, None, outs, None) == bg.BG_EINVAL

@@ -29,7 +29,7 @@ def dev(u, x, hel, order):
             torch.tensor(hel.astype(np.int64), device="cuda").to(torch.int32), torch.tensor(order, device="cuda"))
 
 
-@pytest.mark.parametrize("n,prec", [(5, 64), (8, 64), (8, 32), (6, 32), (7, 32), (4, 64), (10, 64), (10, 32)])
+@pytest.mark.parametrize("n,prec", [(5, 64), (8, 64), (8, 32), (6, 32), (7, 32), (4, 64), (4, 32), (6, 64)])
 def test_grad_vs_oracle(gpu_lib, n, prec):
     N = 1024 + 17
     u, x, hel, order = setup(n, N, 40 + n)
@@ -52,8 +52,11 @@ def test_grad_vs_oracle(gpu_lib, n, prec):
         assert np.median(xerr) < 1e-12 and np.quantile(xerr, 0.99) < 1e-8 and xerr.max() < 1e-6
         assert np.median(lerr) < 1e-12 and np.quantile(lerr, 0.99) < 1e-9 and lerr.max() < 1e-6
     else:
-        assert q[0] < 1e-4 and q[1] < 1e-2
-        assert np.median(xerr) < 1e-5 and np.median(lerr) < 1e-5
+        # FP32: the stated median bound, and the 1% tail of events near a zero of the
+        # amplitude, where FP32 loses most digits
+        assert q[0] < 1e-4 and q[1] < 1e-2 and q[2] < 0.5
+        assert np.median(xerr) < 1e-5 and np.quantile(xerr, 0.99) < 1e-2
+        assert np.median(lerr) < 1e-5 and np.quantile(lerr, 0.99) < 1e-2
 
 
 def test_grad_full_size_sampled(gpu_lib):
@@ -97,13 +100,16 @@ def test_grad_closed_form_and_sum_rules(gpu_lib):
     assert np.median(np.abs((q0 * rho[:, :, 2] * g[:, :, 2]).sum(1)) / scale) < 1e-10
 
 
-def test_grad_vs_finite_differences_of_gpu_forward(gpu_lib):
-    """Central differences (h = 1e-6) of log w from bg_generate's FP64 forward."""
-    n, N = 6, 256
+@pytest.mark.parametrize("n,prec,N", [(6, 64, 256), (8, 32, 1024)])
+def test_grad_vs_finite_differences_of_gpu_forward(gpu_lib, n, prec, N):
+    """Central differences (h = 1e-6) of log w from bg_generate's FP64 forward, against the
+    FP64 adjoint (n = 6) and against the FP32 adjoint of the timed workload (n = 8, 1024
+    events)."""
     u, x, hel, order = setup(n, N, 9)
     c = gpu_lib.config(n, prec=64)
     U, X, H, O = dev(u, x, hel, order)
-    gu, gx, _ = gpu_lib.amp2_grad(c, U, X, H, O)
+    print(f"finite differences n={n} adjoint prec={prec} N={N}", flush=True)
+    gu, gx, _ = gpu_lib.amp2_grad(gpu_lib.config(n, prec=prec), U, X, H, O)
 
     def lw(Uv, Xv):
         return gpu_lib.generate(c, N, inputs=dict(uniforms=Uv, x12=Xv, hel=H, order=O), outputs=("logw",))["logw"]
@@ -124,15 +130,22 @@ def test_grad_vs_finite_differences_of_gpu_forward(gpu_lib):
         fdx[:, j] = (lw(U, xp) - lw(U, xm)) / (2 * hx)
     scale = gu.abs().amax(1)
     err = ((gu - fd).abs().amax(1) / scale).cpu().numpy()
-    assert np.median(err) < 1e-6, np.quantile(err, [0.5, 0.9])
-    assert float(((gx - fdx).abs() / gx.abs()).max()) < 1e-5
+    xerr = ((gx - fdx).abs() / gx.abs()).cpu().numpy()
+    print(f"n={n} prec={prec}: grad_u vs FD p50/p90/p99 {np.quantile(err, [0.5, 0.9, 0.99])}, grad_x max {xerr.max():.2e}")
+    if prec == 64:
+        assert np.median(err) < 1e-6, np.quantile(err, [0.5, 0.9])
+        assert float(xerr.max()) < 1e-5
+    else:
+        assert np.median(err) < 1e-4 and np.quantile(err, 0.9) < 1e-2
+        assert np.median(xerr) < 1e-5
 
 
-def test_grad_unsupported_multiplicity(gpu_lib):
-    n, N = 11, 4
+@pytest.mark.parametrize("n,prec", [(9, 32), (12, 64)])
+def test_grad_unsupported_multiplicity(gpu_lib, n, prec):
+    N = 4
     u, x, hel, order = setup(n, N, 3)
     with pytest.raises(gpu_lib.BgError) as e:
-        gpu_lib.amp2_grad(gpu_lib.config(n, prec=32), *dev(u, x, hel, order))
+        gpu_lib.amp2_grad(gpu_lib.config(n, prec=prec), *dev(u, x, hel, order))
     assert e.value.status == gpu_lib.BG_ENOTSUP
 
 

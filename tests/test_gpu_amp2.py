@@ -8,14 +8,9 @@ import torch
 
 from oracle import event
 from paper_1002_3446_amd import inputs
-from tests.parity import check_amp2_fp64, fp32_errors
+from tests.parity import check_amp2_fp64, fp32_errors, lane_forms
 
 pytestmark = pytest.mark.gpu
-
-
-def lane_forms(n, prec):
-    """Lanes-per-event forms the library holds for (n, prec)."""
-    return [1, 2] if (prec == 32 and n >= 9) or (prec == 64 and n >= 6) else [1]
 
 
 @contextlib.contextmanager
@@ -62,10 +57,13 @@ def test_amp2_fp32_error(gpu_lib, n, lanes):
     print(f"amp2 fp32 n={n} lanes={lanes} N={N}", flush=True)
     with lanes_set(gpu_lib, n, 32, lanes):
         got = run_gpu(gpu_lib, n, 32, mom, hel, order)
-    rel = fp32_errors(got, mom, hel, order)
+    rel, sc = fp32_errors(got, mom, hel, order, scaled=True)
     q = np.quantile(rel, [0.5, 0.9, 0.99])
-    print(f"n={n} fp32 rel err median {q[0]:.2e} p90 {q[1]:.2e} p99 {q[2]:.2e}")
-    assert q[0] <= 1e-4
+    print(f"n={n} fp32 rel err median {q[0]:.2e} p90 {q[1]:.2e} p99 {q[2]:.2e} max {rel.max():.2e}; "
+          f"relative to the event's size: max {sc.max():.2e}")
+    # the stated FP32 bound (median), and the tail in units of max(|A|^2, Parke-Taylor size):
+    # events nearest a zero of the amplitude lose the most relative digits, not absolute ones
+    assert q[0] <= 1e-4 and sc.max() <= 1e-4
 
 
 def test_amp2_empty_and_single(gpu_lib):

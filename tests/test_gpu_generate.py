@@ -9,7 +9,7 @@ import torch
 from oracle import event, pdf
 from oracle.weight import neumaier
 from paper_1002_3446_amd import inputs
-from tests.parity import check_amp2_fp64, fp32_errors
+from tests.parity import check_amp2_fp64, check_amp2_fp64_real, fp32_errors, fp32_errors_real, lane_forms
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,8 @@ def cfg_c1(bg, n=8, prec=32, seed=0xB6000001, **kw):
 def oracle_cfg(c):
     return event.config(n=c.n, sqrt_s=c.sqrt_s, use_pdf=c.use_pdf, pdf_a=c.pdf_a, pdf_b=c.pdf_b,
                         tau_min=c.tau_min, alpha_s=c.alpha_s, pt_min=c.pt_min, eta_max=c.eta_max,
-                        dr_min=c.dr_min, random_order=c.random_order, seed=c.seed, first_event=c.first_event)
+                        dr_min=c.dr_min, random_order=c.random_order, seed=c.seed, first_event=c.first_event,
+                        polarisation=c.polarisation)
 
 
 def to_np(res):
@@ -91,12 +92,24 @@ def compare_events(g, o, ocfg, prec):
     both = np.isfinite(o["rmin"])
     assert np.all(np.abs(g["obs"][both, 1] - o["rmin"][both]) <= (1e-11 + 1e3 * mrel[both]) * o["rmin"][both])
     extra = 2 * n * mrel
-    if prec == 64:
+    real = bool(ocfg.get("polarisation", 0))
+    if prec == 64 and real:
+        stats = check_amp2_fp64_real(g["amp2"], o["mom_cm"], o["psi"], o["order"], extra_rel=extra)
+    elif prec == 64:
         stats = check_amp2_fp64(g["amp2"], o["mom_cm"], o["hel"], o["order"], extra_rel=extra)
     else:
-        rel = fp32_errors(g["amp2"], o["mom_cm"], o["hel"], o["order"])
-        stats = dict(median=float(np.median(rel)), p99=float(np.quantile(rel, 0.99)))
-        assert stats["median"] <= 1e-4
+        if real:
+            rel = fp32_errors_real(g["amp2"], o["mom_cm"], o["psi"], o["order"])
+            stats = dict(median=float(np.median(rel)), p99=float(np.quantile(rel, 0.99)), max=float(rel.max()))
+        else:
+            rel, sc = fp32_errors(g["amp2"], o["mom_cm"], o["hel"], o["order"], scaled=True)
+            stats = dict(median=float(np.median(rel)), p99=float(np.quantile(rel, 0.99)), max=float(rel.max()),
+                         scaled_p99=float(np.quantile(sc, 0.99)), scaled_max=float(sc.max()))
+        # the stated FP32 bound (median), and the tail in units of the event's size (events
+        # near a zero of the amplitude lose all relative precision in FP32, but never more
+        # than 1e-4 of max(|A|^2, its Parke-Taylor size); measured at most 2e-6)
+        assert stats["median"] <= 1e-4, stats
+        assert real or stats["scaled_max"] <= 1e-4, stats
     # weights: zero exactly when failing; otherwise weight / |A|^2 (flux, phase-space volume,
     # colour, density and unit factors) agrees with the oracle's product formula
     assert np.all(g["weight"][~g["pass"].astype(bool)] == 0.0)
@@ -139,7 +152,7 @@ def test_pdf_events(gpu_lib, n, prec):
     print(compare_events(g, o, oc, prec))
 
 
-@pytest.mark.parametrize("n,prec", [(7, 64), (9, 32), (12, 32), (10, 64)])
+@pytest.mark.parametrize("n,prec", [(9, 32), (6, 64)])
 def test_lane_forms_agree(gpu_lib, n, prec):
     """bg_generate with one and with two lanes per event: identical draws, kinematics and
     cut flags; |A|^2 and weights within the recursion precision's rounding (FP64 against
@@ -162,7 +175,7 @@ def test_lane_forms_agree(gpu_lib, n, prec):
     oc["tau_min"] = pdf.tau_min(n, 20.0, 14000.0)
     print(compare_events(two, event.generate(oc, np.arange(N)), oc, prec))
     if prec == 32:
-        same_events(two, one, n)
+        same_events(two, one, n, exact=False)
     exact = math.fsum(two["weight"].tolist())
     assert abs((two["acc"][0] + two["acc"][1]) - exact) <= 2 * EPS * np.abs(two["weight"]).sum()
 
@@ -246,16 +259,19 @@ def test_determinism_split_and_shape(gpu_lib):
     assert abs((tot(p1) + tot(p2)) - tot(a)) <= 4 * EPS * sabs
 
 
-def same_events(m, s, n, exact=False):
-    """Persistent-launch and single-class results of the same class: draws, kinematics and
-    cut flags identical, FP32 |A|^2 and weights equal to FP32 rounding.  The two kernels
-    contract multiply-adds differently, so ill-conditioned events (near a zero of the
-    amplitude, where one FP32 result can even round to exactly zero) may differ by their
-    FP32 error: relative to the larger of the two, median < 1e-5, at most 1% of the events
-    (or 2) beyond 1e-2 and at most 0.2% (or 1) beyond 0.1."""
+def same_events(m, s, n, exact=True):
+    """Two evaluations of the same class: draws, kinematics and cut flags identical; with
+    exact, every output bitwise equal (the same device code evaluates each event, whatever
+    the launch); otherwise (different lane forms of the FP32 recursion) |A|^2 and weights
+    equal to FP32 rounding, which ill-conditioned events (near a zero of the amplitude,
+    where one FP32 result can even round to exactly zero) amplify: relative to the larger
+    of the two, median < 1e-5, at most 1% of the events (or 2) beyond 1e-2 and at most
+    0.2% (or 1) beyond 0.1."""
     for k in ("hel", "order", "pass", "momenta", "obs", "x12", "uniforms") + (("amp2", "weight") if exact else ()):
         if k in m:
             assert np.array_equal(m[k], s[k]), (n, k)
+    if exact:
+        return
     bits = (m["hel"][:, None] >> np.arange(n)) & 1
     live = (bits.sum(1) >= 2) & (bits.sum(1) <= n - 2)   # amplitudes that do not vanish identically
     for k in ("amp2", "weight"):
@@ -268,6 +284,20 @@ def same_events(m, s, n, exact=False):
             assert np.sum(rel > 0.1) <= max(1, 0.002 * rel.size), (n, k)
 
 
+def single_ref(bg, c, N, mode, outputs=None):
+    """The single-class run a class of a multi-class call must reproduce bitwise: the
+    persistent launch evaluates n = 9 with two lanes per event."""
+    outputs = outputs or ALL
+    if not (mode == 1 and c.n == 9 and c.prec == 32):
+        return to_np(bg.generate(c, N, outputs=outputs))
+    old = bg.get_lanes(9, 32)
+    bg.set_lanes(9, 32, 2)
+    try:
+        return to_np(bg.generate(c, N, outputs=outputs))
+    finally:
+        bg.set_lanes(9, 32, old)
+
+
 @pytest.fixture(params=[1, 0, 2], ids=["persistent", "sequential", "concurrent"])
 def mixed_mode(request, gpu_lib):
     old = gpu_lib.get_mixed_launch()
@@ -276,23 +306,19 @@ def mixed_mode(request, gpu_lib):
     gpu_lib.set_mixed_launch(old)
 
 
-def test_two_kernel_form_matches_single_kernel(gpu_lib):
-    """FP32 n <= 8 calls of at least 2^20 events run as a kinematics and a recursion kernel,
-    smaller calls as one kernel: for the same events (the tail of a 2^20 + 37 event call,
-    and a separate call of those 5000 events) draws, kinematics, cut flags and observables
-    are identical, |A|^2 and weights equal to FP32 rounding (the two forms contract the
-    recursion's multiply-adds differently)."""
+def test_call_size_independence(gpu_lib):
+    """FP32 n <= 8 stages its kinematics in chunks of at most 2^21 events: the tail of a
+    2^20 + 37 event call and a separate call of those 5000 events agree bitwise in every
+    per-event output."""
     n, N, tail = 8, (1 << 20) + 37, 5000
     c = cfg_c1(gpu_lib, n=n, prec=32, seed=4242)
-    outs = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12")
-    print("generate n=8 fp32 N=2^20+37 (two-kernel form) and its tail alone", flush=True)
+    outs = ("weight", "amp2", "obs", "pass", "momenta", "hel", "order", "x12", "logw")
+    print("generate n=8 fp32 N=2^20+37 and its tail alone", flush=True)
     big = to_np(gpu_lib.generate(c, N, outputs=outs))
     c2 = cfg_c1(gpu_lib, n=n, prec=32, seed=4242, first_event=N - tail)
     small = to_np(gpu_lib.generate(c2, tail, outputs=outs))
-    sub = {k: v[N - tail:] for k, v in big.items()}
-    diff = {k: int(np.sum(sub[k] != small[k])) for k in outs}
-    print("differing entries per output", diff)
-    same_events(sub, small, n, exact=False)
+    for k in outs:
+        assert np.array_equal(big[k][N - tail:], small[k]), k
 
 
 def test_mixed_classes_match_single(gpu_lib, mixed_mode):
@@ -300,9 +326,9 @@ def test_mixed_classes_match_single(gpu_lib, mixed_mode):
     counts = [3000, 2000, 700]
     mixed = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=ALL)]
     for c, N, m in zip(cfgs, counts, mixed):
-        s = to_np(gpu_lib.generate(c, N, outputs=ALL))
-        same_events(m, s, c.n, exact=mixed_mode != 1)
-        assert abs((m["acc"][0] + m["acc"][1]) - (s["acc"][0] + s["acc"][1])) <= 1e-4 * np.abs(s["weight"]).sum()
+        s = single_ref(gpu_lib, c, N, mixed_mode)
+        same_events(m, s, c.n)
+        assert abs((m["acc"][0] + m["acc"][1]) - (s["acc"][0] + s["acc"][1])) <= 4 * EPS * np.abs(s["weight"]).sum()
     again = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=ALL)]
     for m, a in zip(mixed, again):
         for k in m:
@@ -331,9 +357,9 @@ def test_full_size_sampled(gpu_lib):
     assert np.all(np.abs(x12 - o["x12"]) <= 1e-14 * o["x12"] + x_bound(oc, o["x12"]))
     flip = ps != o["pass_"]
     assert np.all(o["margin"][flip] < 1e-9)
-    rel = fp32_errors(amp, o["mom_cm"], o["hel"], o["order"])
-    print("n=8 fp32 sampled rel err quantiles", np.quantile(rel, [0.5, 0.9, 0.99]))
-    assert np.median(rel) <= 1e-4
+    rel, sc = fp32_errors(amp, o["mom_cm"], o["hel"], o["order"], scaled=True)
+    print("n=8 fp32 sampled rel err quantiles", np.quantile(rel, [0.5, 0.9, 0.99]), "scaled max", sc.max())
+    assert np.median(rel) <= 1e-4 and sc.max() <= 1e-4
 
 
 def test_n12_full_size_fp32_vs_fp64(gpu_lib):
@@ -371,27 +397,38 @@ def test_n12_full_size_fp32_vs_fp64(gpu_lib):
     assert np.median(rel64) <= 1e-12 and np.quantile(rel64, 0.9) <= 1e-10
 
 
-def test_mixed_full_size_sampled(gpu_lib):
-    """The mixed workload as timed: n = 4..12 with 2^(26-n) events each in one call with the
-    tuned strategy; per class, sampled events against the oracle and the compensated total
-    against the exact sum of the weights."""
+@pytest.mark.parametrize("mode", [1, 0], ids=["persistent", "sequential"])
+def test_mixed_full_size_vs_oracle(gpu_lib, mode):
+    """The mixed workload as timed: n = 4..12 with 2^(26-n) events each (8,372,224 events) in
+    one call, as one persistent launch and one class after another; per class, sampled
+    events (first, last and 60 more) against the oracle element by element (draws bit-exact,
+    x, momenta, cuts, observables, |A|^2 and weights), and the compensated total against the
+    exact sum of all of the class's weights."""
     ns = list(range(4, 13))
     cfgs = [cfg_c1(gpu_lib, n=n, prec=32, seed=0xB6000003 + n) for n in ns]
     counts = [1 << (26 - n) for n in ns]
-    print("mixed n=4..12 at 2^(26-n) events", flush=True)
-    res = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=("weight", "amp2", "pass", "x12", "acc"))]
+    old = gpu_lib.get_mixed_launch()
+    gpu_lib.set_mixed_launch(mode)
+    try:
+        print(f"mixed n=4..12 at 2^(26-n) events, mode {mode}", flush=True)
+        res = gpu_lib.generate(cfgs, counts, outputs=ALL)
+        torch.cuda.synchronize()
+    finally:
+        gpu_lib.set_mixed_launch(old)
     rng = np.random.default_rng(2)
     for c, N, m in zip(cfgs, counts, res):
-        w = m["weight"]
-        assert abs(m["acc"][0] + m["acc"][1] - math.fsum(w.tolist())) <= 2 * EPS * np.abs(w).sum(), c.n
+        w = m["weight"].cpu().numpy()
+        acc = m["acc"].cpu().numpy()
+        assert abs(acc[0] + acc[1] - math.fsum(w.tolist())) <= 2 * EPS * np.abs(w).sum(), c.n
         idx = np.unique(np.concatenate([[0, N - 1], rng.integers(0, N, 60)]))
+        it = torch.tensor(idx, device="cuda")
+        g = to_np({k: v[it] for k, v in m.items() if k != "acc"})
         oc = oracle_cfg(c)
+        oc["tau_min"] = pdf.tau_min(c.n, 20.0, 14000.0)
         o = event.generate(oc, idx)
-        assert np.all(np.abs(m["x12"][idx] - o["x12"]) <= 1e-14 * o["x12"] + x_bound(oc, o["x12"])), c.n
-        flip = m["pass"][idx].astype(bool) != o["pass_"]
-        assert np.all(o["margin"][flip] < 1e-9), c.n
-        rel = fp32_errors(m["amp2"][idx], o["mom_cm"], o["hel"], o["order"])
-        assert np.median(rel) <= 1e-4, (c.n, np.median(rel))
+        stats = compare_events(g, o, oc, 32)
+        print(f"n={c.n} mode {mode}: {stats}")
+        del m
 
 
 def test_mixed_all_multiplicities(gpu_lib, mixed_mode):
@@ -403,8 +440,8 @@ def test_mixed_all_multiplicities(gpu_lib, mixed_mode):
     print("mixed n=4..12 fp32", flush=True)
     mixed = [to_np(r) for r in gpu_lib.generate(cfgs, counts, outputs=ALL)]
     for c, N, m in zip(cfgs, counts, mixed):
-        s = to_np(gpu_lib.generate(c, N, outputs=ALL))
-        same_events(m, s, c.n, exact=mixed_mode != 1)
+        s = single_ref(gpu_lib, c, N, mixed_mode)
+        same_events(m, s, c.n)
         exact = math.fsum(m["weight"].tolist())
         assert abs((m["acc"][0] + m["acc"][1]) - exact) <= 2 * EPS * np.abs(m["weight"]).sum()
 
@@ -418,8 +455,4 @@ def test_mixed_precisions_and_empty_class(gpu_lib, mixed_mode):
     for c, N, m in zip(cfgs, counts, mixed):
         if N == 0:
             continue
-        s = to_np(gpu_lib.generate(c, N, outputs=ALL))
-        if c.prec == 64:   # FP64 classes run the single-class kernel
-            assert np.array_equal(m["weight"], s["weight"]) and np.array_equal(m["amp2"], s["amp2"])
-        else:
-            same_events(m, s, c.n, exact=mixed_mode != 1)
+        same_events(m, single_ref(gpu_lib, c, N, mixed_mode), c.n)
