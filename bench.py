@@ -207,6 +207,25 @@ def recursion_rate(bg, torch, n=8, N=1 << 22, reps=5):
             "hbm_bytes_per_event": 8 * 4 * n + 4 + n + 8}
 
 
+def hist_rate(bg, torch, out, N, reps=5):
+    """Exact histograms of H_T (40 bins) and R_min (36 bins) over one step's events (weights
+    and observables already in device memory): one bg_hist_accumulate call; algorithmic
+    bytes 24 per event (weight + two observables read)."""
+    axes = [(bg.OBS_HT, 40, 0.0, 2000.0), (bg.OBS_RMIN, 36, 0.4, 4.0)]
+    limbs = bg.hist_limbs(axes)
+    bg.hist_accumulate(out["weight"], out["obs"], axes, limbs)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        bg.hist_accumulate(out["weight"], out["obs"], axes, limbs)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"hist_2axes_ms_per_step": ms, "hist_2axes_GBps": 24 * N / (ms * 1e-3) / 1e9}
+
+
 def live_helicities(hel, n, torch):
     """Mask of helicity words with at least two of each helicity (non-vanishing amplitudes)."""
     bits = (hel.unsqueeze(1) >> torch.arange(n, device=hel.device, dtype=hel.dtype)) & 1
@@ -358,6 +377,10 @@ def main():
     ap.add_argument("--events", type=int, default=1 << 24)
     ap.add_argument("--n", type=int, default=8,
                     help="multiplicity of the main line (8, the benchmark workload; others for profiling)")
+    ap.add_argument("--prec", type=int, default=32, choices=(32, 64),
+                    help="recursion precision of the main line (32, the benchmark workload; 64 for profiling)")
+    ap.add_argument("--mixed-only", type=int, default=-1, metavar="MODE",
+                    help="only run the mixed n = 4..12 workload three times in one mixed-launch mode (profiling)")
     ap.add_argument("--no-extras", action="store_true", help="main line only (used under profilers)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--recursion", action="store_true",
@@ -391,7 +414,18 @@ def main():
     torch.cuda.set_device(0)
     outputs = ("weight", "amp2", "obs", "pass", "acc")
     n, N = a.n, a.events
-    cfg = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
+    if a.mixed_only >= 0:
+        bg.set_mixed_launch(a.mixed_only)
+        ns = list(range(4, 13))
+        cfgs = [bg.config(m, prec=32, seed=0xB6000003 + m) for m in ns]
+        counts = [1 << (26 - m) for m in ns]
+        outs = bg.generate(cfgs, counts, outputs=outputs)
+        for _ in range(3):
+            bg.generate(cfgs, counts, outputs=outputs, out_tensors=outs)
+        torch.cuda.synchronize()
+        print(json.dumps({"mixed_mode": a.mixed_only, "events": sum(counts)}), flush=True)
+        return
+    cfg = bg.config(n, prec=a.prec, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=BENCH_SEED.get(n, 0xB6000001))
     wall, ms, out = run_steps(bg, torch, cfg, N, a.steps, a.warmup, outputs)
     ms_step = 1e3 * wall / a.steps
     value = N * a.steps / wall
@@ -400,13 +434,15 @@ def main():
     fe = flops_executed(n)
     # FP32 n <= 8 runs as a kinematics and a recursion kernel per chunk of 2^21 events: the
     # timed unit is then the whole bg_generate call (both kernels, every chunk)
-    if n <= 8:
+    real_t = "float" if a.prec == 32 else "double"
+    peak = PEAK_FP32 if a.prec == 32 else PEAK_FP64
+    if n <= 8 and a.prec == 32:
         kname = f"k_kin<{n}>+k_rec<{n}>"
     else:
-        kname = f"k_generate<{n},float>" if bg.get_lanes(n, 32) == 1 else f"k_generate_g<{n},float,2>"
+        kname = (f"k_generate<{n},{real_t}>" if bg.get_lanes(n, a.prec) == 1 else f"k_generate_g<{n},{real_t},2>")
     achieved = fp * N / (launch_ms * 1e-3)
     line = {
-        "metric": f"events/s at gg->{n - 2}g (n={n}) FP32 recursion (FP64 kinematics and weights), full generation path",
+        "metric": f"events/s at gg->{n - 2}g (n={n}) FP{a.prec} recursion (FP64 kinematics and weights), full generation path",
         "value": value,
         "unit": "events/s",
         "n_gpus": 1,
@@ -416,18 +452,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 recursion + f64 kinematics/weights",
+        "dtype": f"f{a.prec} recursion + f64 kinematics/weights",
         "data": "synthetic: Philox-seeded RAMBO events generated on the device",
         "config": {"workload": f"gg->{n - 2}g ({n} external gluons), {N} events per step, sqrt(S)=14 TeV, "
                                f"x ~ x^-1.3 (1-x)^5 on [{((n - 2) * 20.0 / 14000.0) ** 2:.3g},1), alpha_s=0.118, random helicity and "
                                "colour ordering per event, cuts pT>20 GeV |eta|<2.5 dR>0.4",
-                   "n": n, "events_per_step": N, "prec": 32, "parallelism": "one event per lane, 1 GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": traffic_from_profile(kname),
+                   "n": n, "events_per_step": N, "prec": a.prec, "parallelism": "one event per lane, 1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic_from_profile(kname),
                      "kernel": kname, "launch_ms": launch_ms,
                      "flops_per_event_plain": fp, "flops_per_event_executed": fe,
                      "executed_tflops": fe * N / (launch_ms * 1e-3) / 1e12,
-                     "executed_frac": fe * N / (launch_ms * 1e-3) / PEAK_FP32},
+                     "executed_frac": fe * N / (launch_ms * 1e-3) / peak},
         "paper_context": {"tesla_fp32_n8_events_per_s": PAPER_N8_EVENTS_PER_S,
                           "note": "paper Table 1, NVIDIA Tesla, real polarisations, LHAPDF; not the same workload"},
     }
@@ -478,6 +514,7 @@ def main():
             extras[f"n{nr}_realpol_fp32_launch_ms"] = lm
             extras[f"n{nr}_realpol_fp32_frac_plain"] = flops_real(nr) * Nr / (lm * 1e-3) / PEAK_FP32
         line["recursion_kernel"] = recursion_rate(bg, torch)
+        extras.update(hist_rate(bg, torch, out, N))
         extras.update(adjoint_rate(bg, torch))
         extras.update(mixed_rate(bg, torch))
         line["extras"] = extras

@@ -148,6 +148,35 @@ int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const 
                  const uint32_t *hel, const uint8_t *order, const double *gout,
                  double *grad_u, double *grad_x, double *logw, void *stream);
 
+/* Exact histograms of event weights (Sec. 4: the distributions of Fig. 3, accumulated over
+ * many calls as in Fig. 2).  One axis bins one observable column of bg_outputs.obs
+ * (0: H_T, 1: R_min) uniformly on [lo, hi) into nbins; each axis also has an underflow
+ * (x < lo) and an overflow bin (x >= hi or NaN), so it owns nbins + 2 bins, in the order
+ * underflow, 1..nbins, overflow; axes follow one another.  Per bin, sum w and sum w^2 over
+ * the events with w != 0 are accumulated EXACTLY, as fixed-point integers of
+ * BG_HIST_LIMBS limbs (2^-160 resolution; weights must be finite, non-negative and below
+ * 2^112): in any order, over any number of calls, the totals are bitwise reproducible, and
+ * bg_hist_read returns each as the correctly rounded double of the exact sum (the paper's
+ * Kahan sums, without their residual error). */
+typedef struct {
+  int32_t column;  /* 0: H_T, 1: R_min */
+  int32_t nbins;   /* >= 1; at most 400 bins (nbins + 2 summed over axes) per call */
+  double lo, hi;   /* finite, lo < hi; bin b (1..nbins) covers lo + (b-1)(hi-lo)/nbins .. */
+} bg_hist_axis;
+
+#define BG_HIST_LIMBS 12
+
+/* Adds N events (weight [N] FP64, obs [N][2] FP64, device) into limbs: a device array of
+ * [sum over axes of (nbins + 2)][2][BG_HIST_LIMBS] int64 (per bin: sum w, then sum w^2),
+ * zeroed by the caller before the first call and kept between calls.  N <= 2^30 per call.
+ * naxes 1..8, axes a host array.  Errors: BG_EINVAL. */
+int bg_hist_accumulate(int64_t N, const double *weight, const double *obs, int naxes, const bg_hist_axis *axes,
+                       int64_t *limbs, void *stream);
+
+/* out: device [sum over axes of (nbins + 2)][2] FP64: per bin (sum w, sum w^2), each the
+ * correctly rounded double of its exact sum.  limbs are read only. */
+int bg_hist_read(int naxes, const bg_hist_axis *axes, const int64_t *limbs, double *out, void *stream);
+
 /* Validation of the per-event inputs that bg_amp2 and bg_amp2_grad take unchecked (the
  * ordering and helicity conventions above): writes to first_bad (a device int64_t) the
  * smallest event index whose order row [N][n] is not a permutation of 0..n-1 or whose

@@ -57,12 +57,22 @@ class BgOutputs(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in OUTPUT_FIELDS]
 
 
+class BgHistAxis(ctypes.Structure):
+    _fields_ = [("column", ctypes.c_int32), ("nbins", ctypes.c_int32), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double)]
+
+
+HIST_LIMBS = 12
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _lib.bg_generate.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int, _i64p, ctypes.POINTER(BgInputs),
                              ctypes.POINTER(BgOutputs), ctypes.c_void_p]
 _lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 5
 _lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 9
 _lib.bg_check_events.argtypes = [ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 4
+_lib.bg_hist_accumulate.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.POINTER(BgHistAxis), ctypes.c_void_p, ctypes.c_void_p]
+_lib.bg_hist_read.argtypes = [ctypes.c_int, ctypes.POINTER(BgHistAxis), ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_void_p]
 _lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
 _lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.bg_set_lanes.argtypes = [ctypes.c_int] * 3
@@ -71,7 +81,7 @@ _lib.bg_set_mixed_launch.argtypes = [ctypes.c_int]
 _lib.bg_get_mixed_launch.argtypes = []
 _lib.bg_strerror.restype = ctypes.c_char_p
 _lib.bg_strerror.argtypes = [ctypes.c_int]
-for _f in ("bg_generate", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
+for _f in ("bg_generate", "bg_hist_accumulate", "bg_hist_read", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
            "bg_set_mixed_launch", "bg_get_mixed_launch", "bg_set_lanes", "bg_get_lanes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -184,6 +194,43 @@ def generate(cfgs, counts, inputs=None, outputs=("weight", "amp2", "obs", "pass"
     st = _lib.bg_generate(carr, k, narr, ins, outs, _stream(torch.device(device)))
     _check("bg_generate", st)
     return results[0] if single else results
+
+
+OBS_HT, OBS_RMIN = 0, 1
+
+
+def _axes(axes):
+    """axes: sequence of (column, nbins, lo, hi) -> ctypes array, total bins."""
+    arr = (BgHistAxis * len(axes))(*[BgHistAxis(int(c), int(nb), float(lo), float(hi)) for c, nb, lo, hi in axes])
+    return arr, sum(int(a[1]) + 2 for a in axes)
+
+
+def hist_limbs(axes, device="cuda"):
+    """A zeroed limb array for bg_hist_accumulate over these axes."""
+    _, total = _axes(axes)
+    return torch.zeros((total, 2, HIST_LIMBS), dtype=torch.int64, device=device)
+
+
+def hist_accumulate(weight, obs, axes, limbs):
+    """Adds the events (weight [N], obs [N, 2] float64) into limbs (hist_limbs), exactly."""
+    arr, total = _axes(axes)
+    N = weight.shape[0]
+    st = _lib.bg_hist_accumulate(N, _ptr(weight, torch.float64, (N,), "weight"), _ptr(obs, torch.float64, (N, 2), "obs"),
+                                 len(axes), arr, _ptr(limbs, torch.int64, (total, 2, HIST_LIMBS), "limbs"),
+                                 _stream(limbs.device))
+    _check("bg_hist_accumulate", st)
+    return limbs
+
+
+def hist_read(axes, limbs):
+    """[total bins, 2] float64: (sum w, sum w^2) per bin, underflow and overflow included, in
+    axis order; each the correctly rounded exact sum."""
+    arr, total = _axes(axes)
+    out = torch.empty((total, 2), dtype=torch.float64, device=limbs.device)
+    st = _lib.bg_hist_read(len(axes), arr, _ptr(limbs, torch.int64, (total, 2, HIST_LIMBS), "limbs"),
+                           _ptr(out, torch.float64, (total, 2), "out"), _stream(limbs.device))
+    _check("bg_hist_read", st)
+    return out
 
 
 # BG_DEBUG=1 in the environment: amp2 and amp2_grad validate their orderings and helicity

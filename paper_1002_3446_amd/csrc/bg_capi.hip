@@ -643,6 +643,51 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+int hist_axes(int naxes, const bg_hist_axis* axes, HistAxes& A) {
+  if (naxes < 1 || naxes > kHistMaxAxes || !axes) return BG_EINVAL;
+  std::memset(&A, 0, sizeof(A));
+  A.naxes = naxes;
+  int total = 0;
+  for (int a = 0; a < naxes; ++a) {
+    const bg_hist_axis& x = axes[a];
+    if ((x.column != 0 && x.column != 1) || x.nbins < 1 || !(std::isfinite(x.lo) && std::isfinite(x.hi)) ||
+        !(x.lo < x.hi))
+      return BG_EINVAL;
+    A.axis[a] = HistAxis{x.column, x.nbins, total, x.lo, x.hi};
+    total += x.nbins + 2;
+    if (total > kHistMaxBinsTotal) return BG_EINVAL;
+  }
+  A.total_bins = total;
+  return BG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bg_hist_accumulate(int64_t N, const double* weight, const double* obs, int naxes, const bg_hist_axis* axes,
+                       int64_t* limbs, void* stream) {
+  HistAxes A;
+  int st = hist_axes(naxes, axes, A);
+  if (st != BG_OK) return st;
+  if (N < 0 || N > (int64_t(1) << 30) || !limbs) return BG_EINVAL;
+  if (N == 0) return BG_OK;
+  if (!weight || !obs) return BG_EINVAL;
+  return from_hip(launch_hist_accumulate(N, weight, obs, A, limbs, cu_count(), (hipStream_t)stream));
+}
+
+int bg_hist_read(int naxes, const bg_hist_axis* axes, const int64_t* limbs, double* out, void* stream) {
+  HistAxes A;
+  int st = hist_axes(naxes, axes, A);
+  if (st != BG_OK) return st;
+  if (!limbs || !out) return BG_EINVAL;
+  return from_hip(launch_hist_read(A, limbs, out, (hipStream_t)stream));
+}
+
 int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, const uint8_t* order,
             double* amp2_out, void* stream) {
   const Launchers* L = table(n, prec);

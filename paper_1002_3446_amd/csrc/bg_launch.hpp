@@ -113,4 +113,21 @@ hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, in
                                      const Tile* tiles, int ntiles, int* counter, double* stage, double* partials,
                                      int grid, hipStream_t s);
 
+// Histogram axes of one bg_hist_accumulate / bg_hist_read call (bg_hist.hip): axis a
+// reads obs column `column`, bins [lo, hi) into nbins, and owns bins first_bin ..
+// first_bin + nbins + 1 (underflow, nbins, overflow) of the call's limb array.
+constexpr int kHistMaxAxes = 8;
+constexpr int kHistMaxBinsTotal = 400;  // bins over all axes of one call (LDS of the accumulation)
+struct HistAxis {
+  int32_t column, nbins, first_bin;
+  double lo, hi;
+};
+struct HistAxes {
+  int32_t naxes, total_bins;
+  HistAxis axis[kHistMaxAxes];
+};
+hipError_t launch_hist_accumulate(int64_t N, const double* weight, const double* obs, const HistAxes& A,
+                                  int64_t* limbs, int cus, hipStream_t s);
+hipError_t launch_hist_read(const HistAxes& A, const int64_t* limbs, double* out, hipStream_t s);
+
 }  // namespace bgk
