@@ -124,6 +124,20 @@ typedef struct {
 int bg_generate(const bg_config *cfgs, int ncfg, const int64_t *counts,
                 const bg_inputs *ins, const bg_outputs *outs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bg_generate for ONE class (cfg, count,
+ * in, out as bg_generate's entries; in may be NULL) with no allocation and no copy of its
+ * own.  Every buffer the call needs lives in a library array that each GPU holds from the
+ * first such call until the process ends (about 27 MiB): the inverse-CDF table of the
+ * density last used (rebuilt by a small kernel when the density changes), the partials of
+ * the compensated sums and the split form's staging (chunks of 2^16 events).  The kernels,
+ * the partial layout and their reduction are bg_generate's, so every per-event output and
+ * the totals equal bg_generate's bitwise.  count <= 2^24 (else BG_EINVAL).  All calls on
+ * one GPU share that array and it keeps the last call's contents: calls that overlap on one
+ * GPU (other streams, other threads) race; order them.  Errors as bg_generate. */
+int bg_generate_noalloc(const bg_config *cfg, int64_t count, const bg_inputs *in, const bg_outputs *out,
+                        void *stream);
+
 /* |A(sigma; h)|^2 for given physical momenta (Sec. 3, Eqs. 3.1, 3.2, 3.6).
  * mom [N][n][4] FP64, hel [N], order [N][n]; amp2_out [N] FP64.  Span invariants K^2
  * are formed in FP64 for both precisions.  N = 0 is a no-op. */

@@ -66,6 +66,8 @@ HIST_LIMBS = 12
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _lib.bg_generate.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int, _i64p, ctypes.POINTER(BgInputs),
                              ctypes.POINTER(BgOutputs), ctypes.c_void_p]
+_lib.bg_generate_noalloc.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64, ctypes.POINTER(BgInputs),
+                                     ctypes.POINTER(BgOutputs), ctypes.c_void_p]
 _lib.bg_amp2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 5
 _lib.bg_amp2_grad.argtypes = [ctypes.POINTER(BgConfig), ctypes.c_int64] + [ctypes.c_void_p] * 9
 _lib.bg_check_events.argtypes = [ctypes.c_int, ctypes.c_int64] + [ctypes.c_void_p] * 4
@@ -81,7 +83,7 @@ _lib.bg_set_mixed_launch.argtypes = [ctypes.c_int]
 _lib.bg_get_mixed_launch.argtypes = []
 _lib.bg_strerror.restype = ctypes.c_char_p
 _lib.bg_strerror.argtypes = [ctypes.c_int]
-for _f in ("bg_generate", "bg_hist_accumulate", "bg_hist_read", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
+for _f in ("bg_generate", "bg_generate_noalloc", "bg_hist_accumulate", "bg_hist_read", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
            "bg_set_mixed_launch", "bg_get_mixed_launch", "bg_set_lanes", "bg_get_lanes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -194,6 +196,27 @@ def generate(cfgs, counts, inputs=None, outputs=("weight", "amp2", "obs", "pass"
     st = _lib.bg_generate(carr, k, narr, ins, outs, _stream(torch.device(device)))
     _check("bg_generate", st)
     return results[0] if single else results
+
+
+def generate_noalloc(cfg, N, out_tensors, inputs=None, device="cuda"):
+    """bg_generate_noalloc for one class into caller-allocated tensors (out_tensors: dict of
+    output name -> tensor, shapes as in generate); the library allocates nothing."""
+    outs = BgOutputs()
+    for name, t in out_tensors.items():
+        dt, sh = _OUT_SPEC[name]
+        setattr(outs, name, _ptr(t, dt, sh(N, cfg.n), name))
+    ins = None
+    if inputs is not None:
+        ins = BgInputs()
+        n = cfg.n
+        ins.uniforms = _ptr(inputs.get("uniforms"), torch.float64, (N, 4 * (n - 2)), "uniforms")
+        ins.x12 = _ptr(inputs.get("x12"), torch.float64, (N, 2), "x12")
+        ins.hel = _ptr(inputs.get("hel"), torch.int32, (N,), "hel")
+        ins.order = _ptr(inputs.get("order"), torch.uint8, (N, n), "order")
+    st = _lib.bg_generate_noalloc(ctypes.byref(cfg), N, ctypes.byref(ins) if ins is not None else None,
+                                  ctypes.byref(outs), _stream(torch.device(device)))
+    _check("bg_generate_noalloc", st)
+    return out_tensors
 
 
 OBS_HT, OBS_RMIN = 0, 1

@@ -458,9 +458,93 @@ __global__ void k_check_final(int64_t* first_bad) {
   if (threadIdx.x == 0 && first_bad[0] == INT64_MAX) first_bad[0] = -1;
 }
 
+// ----------------------------------------------------------------------------------------
+// Allocation-free generation (bg_generate_noalloc).  Every device buffer such a call needs
+// lives in one file-scope array, `scratch`, which each GPU holds once until the process
+// ends (about 27 MiB): the inverse-CDF table of the density last used, the compensated-sum
+// partials and their second level, and the staging of the split form (chunks of
+// kNoAllocStage events).  Host code never uses the array's name as an address: its device
+// address is looked up once per device (noalloc_scratch) and passed to the kernels.
+// ----------------------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxEvents = int64_t(1) << 24;
+constexpr int64_t kNoAllocStage = int64_t(1) << 16;
+constexpr size_t round256(size_t doubles) { return (doubles + 31) / 32 * 32; }
+constexpr size_t kNoAllocParts = (size_t)(kNoAllocMaxEvents / 64 + 1);  // workgroups of >= 64 events
+constexpr size_t kOffPdf = 0;
+constexpr size_t kOffParts = kOffPdf + round256((size_t)kPdfSegs * 4);
+constexpr size_t kOffLevel2 = kOffParts + round256(kNoAllocParts * 4);
+constexpr size_t kOffStage = kOffLevel2 + round256((size_t)kFinalizeGroups * 4);
+constexpr size_t kScratchDoubles = kOffStage + round256((size_t)kNoAllocStage * split_words(8));
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+struct NoAllocDevice {
+  double* ptr = nullptr;  // device address of this GPU's scratch
+  bool pdf_valid = false;  // the density whose table scratch holds
+  double a = 0.0, tau = 0.0;
+  int b = 0;
+};
+
+// This device's scratch address (looked up with the device current, once per device) and
+// its table record.
+int noalloc_device(NoAllocDevice** out) {
+  static std::mutex mu;
+  static NoAllocDevice devs[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BG_EHIP;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!devs[dev].ptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return BG_EHIP;
+    }
+    devs[dev].ptr = static_cast<double*>(p);
+  }
+  *out = &devs[dev];
+  return BG_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int bg_generate_noalloc(const bg_config* cfg, int64_t count, const bg_inputs* in, const bg_outputs* out,
+                        void* stream) {
+  if (!cfg || !out) return BG_EINVAL;
+  if (count > kNoAllocMaxEvents) return BG_EINVAL;
+  GenClass G;
+  ClassPlan P;
+  int st = fill_class(*cfg, count, in, out, G);
+  if (st == BG_OK) st = plan_class(*cfg, G, P);
+  if (st != BG_OK) return st;
+  if (count == 0) return BG_OK;
+  if ((size_t)P.nblocks > kNoAllocParts) return BG_EINVAL;
+  NoAllocDevice* D = nullptr;
+  if ((st = noalloc_device(&D)) != BG_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (G.use_pdf && !G.in_x) {
+    // the table of this density, rebuilt in scratch when the density changed
+    const PdfParams& Q = G.pdf;
+    if (!(D->pdf_valid && D->a == Q.a && D->b == Q.b && D->tau == Q.tau)) {
+      if (!pdf_table_finite_host(Q)) return BG_EINVAL;
+      if ((st = from_hip(launch_pdf_table(Q, D->ptr + kOffPdf, s))) != BG_OK) return st;
+      D->pdf_valid = true;
+      D->a = Q.a;
+      D->b = Q.b;
+      D->tau = Q.tau;
+    }
+    G.pdf.tab = D->ptr + kOffPdf;
+  }
+  const bool staged = P.lanes == 1 && (split_form(cfg->n, cfg->prec));
+  GenWork W{out->acc ? D->ptr + kOffParts : nullptr, staged ? D->ptr + kOffStage : nullptr,
+            staged ? kNoAllocStage : 0};
+  st = from_hip(P.fn(G, W, P.block, s));
+  if (st == BG_OK && W.partials)
+    st = from_hip(launch_finalize(W.partials, P.nblocks, D->ptr + kOffLevel2, out->acc, s));
+  return st;
+}
+
 
 int bg_version(void) { return 10100; }
 
