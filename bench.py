@@ -498,6 +498,17 @@ def main():
             extras[f"n12_fp{prec}_events_per_s"] = N12 * st / w12
             extras[f"n12_fp{prec}_launch_ms"] = sum(ms12) / len(ms12)
             extras[f"n12_fp{prec}_frac_plain"] = flops_plain(12) * N12 / (sum(ms12) / len(ms12) * 1e-3) / (PEAK_FP32 if prec == 32 else PEAK_FP64)
+        # the W-tensor form of the recursion (Eqs. 3.3-3.4, 16 lanes per event)
+        for nw, pw in ((12, 32), (10, 32), (10, 64)):
+            cw = bg.config(nw, prec=pw, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000002)
+            old = bg.get_form(nw, pw)
+            bg.set_form(nw, pw, bg.FORM_WTENSOR)
+            try:
+                ww, msw, _ = run_steps(bg, torch, cw, 1 << 22, 2, 1, outputs)
+            finally:
+                bg.set_form(nw, pw, old)
+            extras[f"n{nw}_fp{pw}_wtensor_events_per_s"] = (1 << 22) * 2 / ww
+            extras[f"n{nw}_fp{pw}_wtensor_launch_ms"] = sum(msw) / len(msw)
         c12a = bg.config(12, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000002)
         c12b = bg.config(12, prec=64, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000002)
         r32 = bg.generate(c12a, 1 << 18, outputs=("amp2", "hel"))
@@ -513,6 +524,10 @@ def main():
             extras[f"n{nr}_realpol_fp32_events_per_s"] = Nr * 3 / wr
             extras[f"n{nr}_realpol_fp32_launch_ms"] = lm
             extras[f"n{nr}_realpol_fp32_frac_plain"] = flops_real(nr) * Nr / (lm * 1e-3) / PEAK_FP32
+        # the dynamic scale mu = H_T (alpha_s and the density from grids)
+        cd = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=BENCH_SEED[8], dynamic_scale=1)
+        wd, msd, _ = run_steps(bg, torch, cd, N, 3, 1, outputs)
+        extras["n8_dynamic_scale_fp32_events_per_s"] = N * 3 / wd
         line["recursion_kernel"] = recursion_rate(bg, torch)
         extras.update(hist_rate(bg, torch, out, N))
         extras.update(adjoint_rate(bg, torch))

@@ -75,6 +75,20 @@ typedef struct {
                            holds the drawn but unused helicity word */
   uint64_t seed;        /* Philox-4x32-10 key */
   uint64_t first_event; /* event index of the first event (Philox counter offset) */
+  int32_t dynamic_scale;/* 0: fixed alpha_s and density (the fields above);
+                           1: the scale of each event is mu = H_T (Sec. 4, Fig. 3): the weight
+                           takes alpha_s(mu)^(n-2) f(x1, mu) f(x2, mu), read from grids with
+                           linear interpolation (Sec. 3): alpha_s(mu) at one loop with
+                           n_f = 5, alpha_s(mu0) = alpha_s, on 512 nodes uniform in ln mu over
+                           [5, 20000] GeV; ln f(x, mu) with the exponents a + pdf_da ln(mu/mu0),
+                           b + pdf_db ln(mu/mu0) on 64 x 1024 nodes uniform in ln mu and in
+                           ln(x/(1-x)) over x in [1e-6, 1 - 1e-9]; scales and x outside take
+                           the edge values.  x1, x2 are still drawn from f(x) at mu0 (the
+                           ratio enters the weight).  Not for bg_amp2_grad or
+                           bg_generate_noalloc (BG_ENOTSUP) */
+  int32_t reserved;     /* must be 0 */
+  double mu0;           /* GeV, the reference scale of alpha_s and f(x); <= 0 means 91.188 */
+  double pdf_da, pdf_db;/* d a / d ln mu and d b / d ln mu of the density's exponents */
 } bg_config;
 
 /* Optional caller-supplied draws for bg_generate; any NULL field is drawn from Philox.
@@ -219,6 +233,18 @@ int bg_get_launch(int n, int prec, int *block, int *tile_iters);
  * only: |A|^2 agrees to the recursion precision's rounding between the forms. */
 int bg_set_lanes(int n, int prec, int lanes);
 int bg_get_lanes(int n, int prec, int *lanes);
+
+/* Form of the recursion in the single-class kernels of (n, prec) (bg_generate with helicity
+ * states, and bg_amp2): 0 (default) the direct sums of Eqs. 3.1-3.2; 1 the W-tensor form of
+ * Eqs. 3.3-3.4 (with the propagator 1/K^2 that Eq. 3.3 leaves implicit): a 4x4 tensor W per
+ * span removes the double sum of the four-gluon terms, O(n^3) instead of O(n^4) work, at the
+ * price of the tensors' storage.  One event takes 16 lanes (lane (mu, nu) holds W_mu,nu of
+ * every span, the currents are shared through LDS); generation then stages the kinematics
+ * as the split form does.  Built for FP32 n = 8, 10, 11, 12 and FP64 n = 6, 10 (else
+ * BG_ENOTSUP); the persistent mixed launch, real polarisations and bg_amp2_grad keep the
+ * direct form.  |A|^2 agrees with the direct form to the recursion precision's rounding. */
+int bg_set_form(int n, int prec, int form);
+int bg_get_form(int n, int prec, int *form);
 
 /* Strategy for bg_generate calls with several classes (process-wide setting):
  *   0  each class's single-class kernel, one after another on the caller's stream;

@@ -14,7 +14,8 @@ log_weight_int() / log_weight_grad():
 Configuration dictionaries use the keys of the C-ABI's bg_config:
   n, prec (ignored: the oracle is always double), sqrt_s, use_pdf, pdf_a, pdf_b,
   tau_min, alpha_s, pt_min, eta_max, dr_min, random_order, seed, first_event,
-  polarisation (0: helicity states, 1: random real unit vectors, Sec. 3).
+  polarisation (0: helicity states, 1: random real unit vectors, Sec. 3),
+  dynamic_scale (1: alpha_s and the density at mu = H_T from grids), mu0, pdf_da, pdf_db.
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ from math import factorial, lgamma, log, pi
 import numpy as np
 
 from . import cuts as _cuts
-from . import draws, pdf
+from . import draws, pdf, scale
 from .helicity import linear_polarisation, polarisation
 from .ops import NP64, TorchOps
 from .rambo import beams, boost_z, rambo
@@ -32,7 +33,8 @@ from .weight import HBARC2_PB, NC, weight
 
 DEFAULTS = dict(prec=64, sqrt_s=14000.0, use_pdf=1, pdf_a=-1.3, pdf_b=5, tau_min=0.0,
                 alpha_s=0.118, pt_min=20.0, eta_max=2.5, dr_min=0.4, random_order=1,
-                seed=0, first_event=0, polarisation=0)
+                seed=0, first_event=0, polarisation=0, dynamic_scale=0, mu0=91.188, pdf_da=-0.05,
+                pdf_db=0.4)
 
 
 def config(**kw) -> dict:
@@ -121,6 +123,11 @@ def generate(cfg: dict, events) -> dict:
     psi = draws.polarisation_angles(words, n) if real else None
     a2 = amp2_real(mom_cm, psi, order) if real else amp2(mom_cm, hel, order)
     w = weight(a2, s_hat, n, cfg["alpha_s"], ratio, cut["pass_"])
+    if cfg.get("dynamic_scale", 0):
+        g = scale.Grids(cfg["alpha_s"], cfg["mu0"], cfg["pdf_a"], int(cfg["pdf_b"]), cfg["pdf_da"], cfg["pdf_db"],
+                        bool(cfg["use_pdf"]))
+        w = w * np.where(cut["pass_"], scale.weight_ratio(g, n, cut["ht"], x12[:, 0], x12[:, 1], cfg["alpha_s"],
+                                                          cfg["pdf_a"], int(cfg["pdf_b"]), bool(cfg["use_pdf"])), 0.0)
     return dict(x12=x12, rho=rho, hel=hel, order=order, mom=mom, mom_cm=mom_cm, s_hat=s_hat, amp2=a2,
                 weight=w, pass_=cut["pass_"], ht=cut["ht"], rmin=cut["rmin"],
                 margin=cut["margin"], words=words, psi=psi)

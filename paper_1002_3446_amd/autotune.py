@@ -51,32 +51,41 @@ def lane_forms(n, prec):
     return (1, 2) if (prec == 32 and n >= 9) or (prec == 64 and n >= 6) else (1,)
 
 
+def wtensor_forms(n, prec):
+    """Multiplicities whose W-tensor form the library holds."""
+    return (prec == 32 and n in (8, 10, 11, 12)) or (prec == 64 and n in (6, 10))
+
+
 def tune_single(prec=32, scale=0, log=print):
-    """Workgroup size and lanes per event of every single-class kernel."""
+    """Workgroup size, lanes per event and recursion form of every single-class kernel."""
     shapes = {}
     for n in NS:
         N = 1 << max(20 - scale, 26 - n - scale)
         cfg = bg.config(n, prec=prec, seed=0xB6000003 + n)
         out = bg.generate(cfg, N, outputs=("weight", "acc"))
+        cands = [(lanes, 0, block) for lanes in lane_forms(n, prec) for block in (64, 128, 256)]
+        if wtensor_forms(n, prec):
+            cands.append((1, 1, 64))   # the W-tensor kernels take fixed 64-lane workgroups
         best = None
-        for lanes in lane_forms(n, prec):
+        for lanes, form, block in cands:
+            bg.set_form(n, prec, form)
             bg.set_lanes(n, prec, lanes)
-            for block in (64, 128, 256):
-                bg.set_launch(n, prec, block, bg.get_launch(n, prec)[1] or 1)
-                t = _time(lambda: bg.generate(cfg, N, outputs=("weight", "acc"), out_tensors=[out]))
-                log(f"n={n} prec={prec} lanes={lanes} block={block}: {t:.3f} ms for {N} events")
-                if best is None or t < best[0]:
-                    best = (t, block, lanes)
-        shapes[n] = [best[1], bg.get_launch(n, prec)[1], best[2]]
+            bg.set_launch(n, prec, block, bg.get_launch(n, prec)[1] or 1)
+            t = _time(lambda: bg.generate(cfg, N, outputs=("weight", "acc"), out_tensors=[out]))
+            log(f"n={n} prec={prec} form={form} lanes={lanes} block={block}: {t:.3f} ms for {N} events")
+            if best is None or t < best[0]:
+                best = (t, block, lanes, form)
+        shapes[n] = [best[1], bg.get_launch(n, prec)[1], best[2], best[3]]
         bg.set_launch(n, prec, shapes[n][0], shapes[n][1])
         bg.set_lanes(n, prec, shapes[n][2])
+        bg.set_form(n, prec, shapes[n][3])
     return shapes
 
 
 def tune(prec=32, scale=0, log=print):
     shapes = tune_single(prec, scale, log)
     if prec != 32:   # the persistent multi-class kernel is FP32 only
-        return [dict(n=n, prec=prec, block=b, tile_iters=i, lanes=l) for n, (b, i, l) in shapes.items()], None
+        return [dict(n=n, prec=prec, block=b, tile_iters=i, lanes=l, form=f) for n, (b, i, l, f) in shapes.items()], None
     cfgs, counts = mixed_workload(prec, scale)
     outs = bg.generate(cfgs, counts, outputs=("weight", "acc"))
     run = lambda: bg.generate(cfgs, counts, outputs=("weight", "acc"), out_tensors=outs)
@@ -99,7 +108,7 @@ def tune(prec=32, scale=0, log=print):
         modes[name] = _time(run)
     bg.set_mixed_launch(bg.MIXED_PERSISTENT)
     log("mixed workload: " + ", ".join(f"{k} {v:.3f} ms" for k, v in modes.items()))
-    return [dict(n=n, prec=prec, block=b, tile_iters=i, lanes=l) for n, (b, i, l) in shapes.items()], modes
+    return [dict(n=n, prec=prec, block=b, tile_iters=i, lanes=l, form=f) for n, (b, i, l, f) in shapes.items()], modes
 
 
 def main():
@@ -114,6 +123,7 @@ def main():
         for n in NS:
             bg.set_launch(n, prec, 0, 0)   # start from the built-in defaults
             bg.set_lanes(n, prec, 0)
+            bg.set_form(n, prec, 0)
     bg.set_mixed_launch(bg.MIXED_PERSISTENT)
     doc = json.load(open(a.out)) if os.path.exists(a.out) else {}
     shapes = [e for e in doc.get("shapes", []) if e["prec"] not in precs]

@@ -42,6 +42,8 @@ class BgConfig(ctypes.Structure):
         ("tau_min", ctypes.c_double), ("alpha_s", ctypes.c_double), ("pt_min", ctypes.c_double),
         ("eta_max", ctypes.c_double), ("dr_min", ctypes.c_double), ("random_order", ctypes.c_int32),
         ("polarisation", ctypes.c_int32), ("seed", ctypes.c_uint64), ("first_event", ctypes.c_uint64),
+        ("dynamic_scale", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu0", ctypes.c_double),
+        ("pdf_da", ctypes.c_double), ("pdf_db", ctypes.c_double),
     ]
 
 
@@ -79,12 +81,15 @@ _lib.bg_set_launch.argtypes = [ctypes.c_int] * 4
 _lib.bg_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.bg_set_lanes.argtypes = [ctypes.c_int] * 3
 _lib.bg_get_lanes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.bg_set_form.argtypes = [ctypes.c_int] * 3
+_lib.bg_get_form.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.bg_set_mixed_launch.argtypes = [ctypes.c_int]
 _lib.bg_get_mixed_launch.argtypes = []
 _lib.bg_strerror.restype = ctypes.c_char_p
 _lib.bg_strerror.argtypes = [ctypes.c_int]
 for _f in ("bg_generate", "bg_generate_noalloc", "bg_hist_accumulate", "bg_hist_read", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
-           "bg_set_mixed_launch", "bg_get_mixed_launch", "bg_set_lanes", "bg_get_lanes"):
+           "bg_set_mixed_launch", "bg_get_mixed_launch", "bg_set_lanes", "bg_get_lanes", "bg_set_form",
+           "bg_get_form"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -115,10 +120,12 @@ def strerror(status: int) -> str:
 def config(n: int, prec: int = 32, sqrt_s: float = 14000.0, use_pdf: int = 1, pdf_a: float = -1.3,
            pdf_b: int = 5, tau_min: float = 0.0, alpha_s: float = 0.118, pt_min: float = 20.0,
            eta_max: float = 2.5, dr_min: float = 0.4, random_order: int = 1, seed: int = 0,
-           first_event: int = 0, polarisation: int = 0) -> BgConfig:
-    """polarisation: 0 helicity states, 1 random real unit vectors (real currents)."""
+           first_event: int = 0, polarisation: int = 0, dynamic_scale: int = 0, mu0: float = 91.188,
+           pdf_da: float = -0.05, pdf_db: float = 0.4) -> BgConfig:
+    """polarisation: 0 helicity states, 1 random real unit vectors (real currents).
+    dynamic_scale: 1 evaluates alpha_s and the density at mu = H_T (grid interpolation)."""
     return BgConfig(n, prec, sqrt_s, use_pdf, pdf_b, pdf_a, tau_min, alpha_s, pt_min, eta_max, dr_min,
-                    random_order, polarisation, seed, first_event)
+                    random_order, polarisation, seed, first_event, dynamic_scale, 0, mu0, pdf_da, pdf_db)
 
 
 def _ptr(t, dtype, shape, name):
@@ -335,6 +342,20 @@ def get_lanes(n: int, prec: int) -> int:
     return v.value
 
 
+FORM_DIRECT, FORM_WTENSOR = 0, 1
+
+
+def set_form(n: int, prec: int, form: int):
+    """Recursion form of the single-class kernels of (n, prec): FORM_DIRECT or FORM_WTENSOR."""
+    _check("bg_set_form", _lib.bg_set_form(n, prec, form))
+
+
+def get_form(n: int, prec: int) -> int:
+    v = ctypes.c_int()
+    _check("bg_get_form", _lib.bg_get_form(n, prec, ctypes.byref(v)))
+    return v.value
+
+
 MIXED_SEQUENTIAL, MIXED_PERSISTENT, MIXED_CONCURRENT = 0, 1, 2
 
 
@@ -363,6 +384,8 @@ def load_tuning(path: str = TUNING_PATH) -> int:
         set_launch(int(e["n"]), int(e["prec"]), int(e["block"]), int(e["tile_iters"]))
         if "lanes" in e:
             set_lanes(int(e["n"]), int(e["prec"]), int(e["lanes"]))
+        if "form" in e:
+            set_form(int(e["n"]), int(e["prec"]), int(e["form"]))
     if "mixed_mode" in doc:
         set_mixed_launch(int(doc["mixed_mode"]))
     return len(entries)

@@ -70,6 +70,10 @@ def has_real_pol(n: int, p: int) -> bool:
     return n <= 12 if p == 32 else n <= 8
 
 
+def has_wtensor(n: int, p: int) -> bool:
+    return (n == 8 or n >= 10) if p == 32 else n in (6, 10)
+
+
 def units_for(ns, precs=(32, 64), kinds=KINDS):
     """(source, object, defines, expected cost) of every unit; the costliest start first."""
     units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"),
@@ -87,7 +91,8 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
                     forms = (1,)
                 else:
                     forms = tuple(f for f, ok in ((1, has_one_lane(n, p)), (2, has_lane_pairs(n, p)),
-                                                  (3, k == 0 and has_real_pol(n, p))) if ok)
+                                                  (3, k == 0 and has_real_pol(n, p)),
+                                                  (4, has_wtensor(n, p))) if ok)
                 for f in forms:
                     obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}_f{f}.o")
                     cost = n ** 3 * (2 if p == 64 else 1) * (4 if k == 2 else 1)

@@ -25,7 +25,11 @@
   __attribute__((weak)) hipError_t launch_amp2_2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*, \
                                                                   const uint8_t*, double*, int, hipStream_t); \
   __attribute__((weak)) hipError_t launch_generate_real_n##N##_p##P##_k0(const GenClass&, const GenWork&, int, \
-                                                                         hipStream_t);
+                                                                         hipStream_t); \
+  __attribute__((weak)) hipError_t launch_generate_w_n##N##_p##P##_k0(const GenClass&, const GenWork&, int,  \
+                                                                      hipStream_t);                         \
+  __attribute__((weak)) hipError_t launch_amp2_w_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*,   \
+                                                                  const uint8_t*, double*, int, hipStream_t);
 #define BG_DECL(N) BG_DECL_ONE(N, 32) BG_DECL_ONE(N, 64)
 namespace bgk {
 BG_DECL(4) BG_DECL(5) BG_DECL(6) BG_DECL(7) BG_DECL(8) BG_DECL(9) BG_DECL(10) BG_DECL(11) BG_DECL(12)
@@ -41,9 +45,11 @@ using namespace bgk;
 
 #define BG_ROW(N)                                                                                       \
   {{launch_generate_n##N##_p32_k0, launch_amp2_n##N##_p32_k1, launch_grad_n##N##_p32_k2,                \
-    launch_generate2_n##N##_p32_k0, launch_amp2_2_n##N##_p32_k1, launch_generate_real_n##N##_p32_k0},   \
+    launch_generate2_n##N##_p32_k0, launch_amp2_2_n##N##_p32_k1, launch_generate_real_n##N##_p32_k0,    \
+    launch_generate_w_n##N##_p32_k0, launch_amp2_w_n##N##_p32_k1},                                       \
    {launch_generate_n##N##_p64_k0, launch_amp2_n##N##_p64_k1, launch_grad_n##N##_p64_k2,                \
-    launch_generate2_n##N##_p64_k0, launch_amp2_2_n##N##_p64_k1, launch_generate_real_n##N##_p64_k0}}
+    launch_generate2_n##N##_p64_k0, launch_amp2_2_n##N##_p64_k1, launch_generate_real_n##N##_p64_k0,    \
+    launch_generate_w_n##N##_p64_k0, launch_amp2_w_n##N##_p64_k1}}
 
 const Launchers* table(int n, int prec) {
   static const Launchers t[9][2] = {BG_ROW(4),  BG_ROW(5),  BG_ROW(6), BG_ROW(7), BG_ROW(8),
@@ -61,6 +67,12 @@ struct Shape {
 std::mutex g_shape_mu;
 Shape g_shape[13][2];
 int g_lanes[13][2];  // lanes per event of single-class kernels (0 = default_lanes)
+int g_form[13][2];   // recursion form of single-class kernels: 0 direct, 1 W-tensor
+
+int form_of(int n, int prec) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  return g_form[n][prec == 32 ? 0 : 1];
+}
 
 int lanes_of(int n, int prec) {
   std::lock_guard<std::mutex> lk(g_shape_mu);
@@ -128,6 +140,7 @@ int cu_count() {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHbarc2Pb = 0.3893793721e9;  // (hbar c)^2 in pb GeV^2
 constexpr double kNc = 3.0;
+constexpr double kMuZ = 91.188;  // GeV, the default reference scale (Sec. 4)
 
 double lfact(int k) { return std::lgamma((double)k + 1.0); }
 
@@ -154,7 +167,8 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
   if (c.n < 4 || c.n > 12 || (c.prec != 32 && c.prec != 64)) return BG_ENOTSUP;
   if (count < 0 || (c.polarisation != 0 && c.polarisation != 1) || !(c.sqrt_s > 0) || (c.use_pdf != 0 && c.use_pdf != 1) ||
       (c.random_order != 0 && c.random_order != 1) || !(c.alpha_s > 0) || !(c.pt_min >= 0) ||
-      !(c.eta_max > 0) || !(c.dr_min >= 0))
+      !(c.eta_max > 0) || !(c.dr_min >= 0) || (c.dynamic_scale != 0 && c.dynamic_scale != 1) || c.reserved != 0 ||
+      !std::isfinite(c.pdf_da) || !std::isfinite(c.pdf_db) || !(c.mu0 < 1e300))
     return BG_EINVAL;
   std::memset(&G, 0, sizeof(G));
   G.count = count;
@@ -164,6 +178,9 @@ int fill_class(const bg_config& c, int64_t count, const bg_inputs* in, const bg_
   G.use_pdf = c.use_pdf;
   G.random_order = c.random_order;
   G.polarisation = c.polarisation;
+  G.dynamic_scale = c.dynamic_scale;
+  G.lmu0 = std::log(c.mu0 > 0 ? c.mu0 : kMuZ);
+  G.log_alpha0 = std::log(c.alpha_s);
   G.sqrt_s = c.sqrt_s;
   G.pt_min = c.pt_min;
   G.eta_max = c.eta_max;
@@ -344,6 +361,69 @@ int pdf_table(const PdfParams& P, const double** out, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------------------
+// Grids of the dynamic scale (ScaleGrid, bg_device.hpp): alpha_s at one loop,
+//   alpha_s(mu) = alpha_s(mu0) / (1 + alpha_s(mu0) b0 ln(mu^2 / mu0^2)),  b0 = (33 - 2 n_f) / (12 pi),
+// n_f = 5, and ln f(x, mu) = (a + da L) ln x + (b + db L) ln(1 - x), L = ln(mu / mu0), at the
+// grid nodes; built on the host once per (alpha_s, mu0, a, b, da, db) and device, kept until
+// the process ends (1 MB each).  BG_EINVAL when the Landau pole lies inside the grid.
+// ----------------------------------------------------------------------------------------
+int scale_grid(const bg_config& c, const GenClass& G, ScaleGrid& out) {
+  struct Entry {
+    int dev;
+    double alpha_s, lmu0, a, da, db;
+    int b;
+    double* d;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BG_EHIP;
+  const double a = c.use_pdf ? c.pdf_a : 0.0, da = c.use_pdf ? c.pdf_da : 0.0, db = c.use_pdf ? c.pdf_db : 0.0;
+  const int b = c.use_pdf ? c.pdf_b : 0;
+  out.lmu_lo = std::log(kGridMuLo);
+  out.dlmu_alpha = (std::log(kGridMuHi) - out.lmu_lo) / (kAlphaNodes - 1);
+  out.dlmu_pdf = (std::log(kGridMuHi) - out.lmu_lo) / (kGridMuNodes - 1);
+  out.y_lo = std::log(kGridXLo) - std::log1p(-kGridXLo);
+  out.dy = (std::log(kGridXHi) - std::log1p(-kGridXHi) - out.y_lo) / (kGridYNodes - 1);
+  std::lock_guard<std::mutex> lk(mu);
+  double* d = nullptr;
+  for (const Entry& e : cache)
+    if (e.dev == dev && e.alpha_s == c.alpha_s && e.lmu0 == G.lmu0 && e.a == a && e.b == b && e.da == da && e.db == db)
+      d = e.d;
+  if (!d) {
+    const double b0 = (33.0 - 2.0 * 5.0) / (12.0 * kPi);
+    std::vector<double> h((size_t)kAlphaNodes + (size_t)kGridMuNodes * kGridYNodes);
+    for (int k = 0; k < kAlphaNodes; ++k) {
+      const double den = 1.0 + c.alpha_s * b0 * 2.0 * (out.lmu_lo + k * out.dlmu_alpha - G.lmu0);
+      if (!(den > 0.0)) return BG_EINVAL;
+      h[k] = c.alpha_s / den;
+    }
+    for (int im = 0; im < kGridMuNodes; ++im) {
+      const double L = out.lmu_lo + im * out.dlmu_pdf - G.lmu0;
+      for (int iy = 0; iy < kGridYNodes; ++iy) {
+        const double y = out.y_lo + iy * out.dy;
+        const double lx = -std::log1p(std::exp(-y)), l1x = -std::log1p(std::exp(y));
+        h[kAlphaNodes + (size_t)im * kGridYNodes + iy] = (a + da * L) * lx + (b + db * L) * l1x;
+      }
+    }
+    for (double v : h)
+      if (!std::isfinite(v)) return BG_EINVAL;
+    if (hipMalloc((void**)&d, h.size() * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return BG_ENOMEM;
+    }
+    if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      return BG_EHIP;
+    }
+    cache.push_back(Entry{dev, c.alpha_s, G.lmu0, a, da, db, b, d});
+  }
+  out.alpha = d;
+  out.lnf = d + kAlphaNodes;
+  return BG_OK;
+}
+
+// ----------------------------------------------------------------------------------------
 // Single-class launches.
 // ----------------------------------------------------------------------------------------
 // Staging of the split form: chunks of at most kStageChunk events (at n = 8, 621 MB).
@@ -351,16 +431,19 @@ constexpr int64_t kStageChunk = int64_t(1) << 21;
 
 struct ClassPlan {
   int lanes, block;
+  bool wform, staged;  // W-tensor form; kinematics staged for a separate recursion kernel
   int64_t nblocks;  // workgroups = compensated partials
   GenerateFn fn;
 };
 
 int plan_class(const bg_config& c, const GenClass& G, ClassPlan& P) {
   const Launchers* L = table(c.n, c.prec);
-  P.lanes = c.polarisation ? 1 : lanes_of(c.n, c.prec);
-  P.fn = c.polarisation ? L->generate_real : (P.lanes == 2 ? L->generate2 : L->generate);
+  P.wform = !c.polarisation && form_of(c.n, c.prec) == 1;
+  P.lanes = (c.polarisation || P.wform) ? 1 : lanes_of(c.n, c.prec);
+  P.fn = c.polarisation ? L->generate_real : (P.wform ? L->generate_w : (P.lanes == 2 ? L->generate2 : L->generate));
   if (!P.fn) return BG_ENOTSUP;
-  P.block = (P.lanes == 1 && split_form(c.n, c.prec)) ? kLdsLanes : shape_of(c.n, c.prec).block;
+  P.staged = P.wform || (P.lanes == 1 && split_form(c.n, c.prec));
+  P.block = P.staged ? kLdsLanes : shape_of(c.n, c.prec).block;
   P.nblocks = (P.lanes * G.count + P.block - 1) / P.block;
   return BG_OK;
 }
@@ -513,6 +596,7 @@ int bg_generate_noalloc(const bg_config* cfg, int64_t count, const bg_inputs* in
                         void* stream) {
   if (!cfg || !out) return BG_EINVAL;
   if (count > kNoAllocMaxEvents) return BG_EINVAL;
+  if (cfg->dynamic_scale) return BG_ENOTSUP;
   GenClass G;
   ClassPlan P;
   int st = fill_class(*cfg, count, in, out, G);
@@ -536,9 +620,10 @@ int bg_generate_noalloc(const bg_config* cfg, int64_t count, const bg_inputs* in
     }
     G.pdf.tab = D->ptr + kOffPdf;
   }
-  const bool staged = P.lanes == 1 && (split_form(cfg->n, cfg->prec));
-  GenWork W{out->acc ? D->ptr + kOffParts : nullptr, staged ? D->ptr + kOffStage : nullptr,
-            staged ? kNoAllocStage : 0};
+  // the staging region holds kNoAllocStage events of n = 8; larger n take shorter chunks
+  const int64_t cap = (int64_t)(kNoAllocStage * split_words(8) / split_words(cfg->n)) / 64 * 64;
+  GenWork W{out->acc ? D->ptr + kOffParts : nullptr, P.staged ? D->ptr + kOffStage : nullptr,
+            P.staged ? cap : 0};
   st = from_hip(P.fn(G, W, P.block, s));
   if (st == BG_OK && W.partials)
     st = from_hip(launch_finalize(W.partials, P.nblocks, D->ptr + kOffLevel2, out->acc, s));
@@ -593,6 +678,23 @@ int bg_set_lanes(int n, int prec, int lanes) {
   return BG_OK;
 }
 
+int bg_set_form(int n, int prec, int form) {
+  const Launchers* L = table(n, prec);
+  if (!L) return BG_ENOTSUP;
+  if (form != 0 && form != 1) return BG_EINVAL;
+  if (form == 1 && !(L->generate_w && L->amp2_w)) return BG_ENOTSUP;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_form[n][prec == 32 ? 0 : 1] = form;
+  return BG_OK;
+}
+
+int bg_get_form(int n, int prec, int* form) {
+  if (!table(n, prec)) return BG_ENOTSUP;
+  if (!form) return BG_EINVAL;
+  *form = form_of(n, prec);
+  return BG_OK;
+}
+
 int bg_get_lanes(int n, int prec, int* lanes) {
   if (!table(n, prec)) return BG_ENOTSUP;
   if (!lanes) return BG_EINVAL;
@@ -620,8 +722,12 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
     if (st != BG_OK) return st;
   }
   hipStream_t s = (hipStream_t)stream;
-  // inverse-CDF tables of the classes that sample x1, x2
+  // inverse-CDF tables of the classes that sample x1, x2; grids of dynamic-scale classes
   for (int k = 0; k < ncfg; ++k) {
+    if (G[k].dynamic_scale && G[k].count > 0) {
+      const int st = scale_grid(cfgs[k], G[k], G[k].grid);
+      if (st != BG_OK) return st;
+    }
     if (!(G[k].use_pdf && !G[k].in_x && G[k].count > 0)) continue;
     const int st = pdf_table(G[k].pdf, &G[k].pdf.tab, s);
     if (st != BG_OK) return st;
@@ -659,7 +765,7 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   // else one buffer reused by every class in turn
   size_t shared_stage = 0;
   for (int k : todo) {
-    if (!(P[k].lanes == 1 && split_form(cfgs[k].n, cfgs[k].prec))) continue;
+    if (!P[k].staged) continue;
     scap[k] = std::min<int64_t>(kStageChunk, (G[k].count + kLdsLanes - 1) / kLdsLanes * kLdsLanes);
     const size_t sb = (size_t)scap[k] * split_words(cfgs[k].n) * sizeof(double);
     if (concurrent) {
@@ -777,7 +883,7 @@ int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, 
   const Launchers* L = table(n, prec);
   if (!L) return BG_ENOTSUP;
   if (N < 0) return BG_EINVAL;
-  const Amp2Fn f = lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2;
+  const Amp2Fn f = form_of(n, prec) == 1 ? L->amp2_w : (lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2);
   if (!f) return BG_ENOTSUP;
   if (N == 0) return BG_OK;
   if (!mom || !hel || !order || !amp2_out) return BG_EINVAL;
@@ -807,7 +913,7 @@ int bg_amp2_grad(const bg_config* cfg, int64_t N, const double* uniforms, const 
   if (N == 0) return BG_OK;
   if (!uniforms || !hel || !order || !grad_u || !grad_x || (cfg->use_pdf && !x12)) return BG_EINVAL;
   if (!(cfg->sqrt_s > 0) || !(cfg->alpha_s > 0) || (cfg->use_pdf != 0 && cfg->use_pdf != 1)) return BG_EINVAL;
-  if (cfg->polarisation != 0) return BG_ENOTSUP;
+  if (cfg->polarisation != 0 || cfg->dynamic_scale != 0) return BG_ENOTSUP;
   GradArgs G{};
   G.count = N;
   G.sqrt_s = cfg->sqrt_s;

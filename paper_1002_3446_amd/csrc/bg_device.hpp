@@ -274,6 +274,58 @@ __host__ __device__ inline void pdf_table_segment(const PdfParams& P, int seg, d
 }
 
 // ----------------------------------------------------------------------------------------
+// Running coupling and scale-dependent density on grids (Sec. 3: alpha_s on a 1-D grid in the
+// renormalisation scale, the densities on a 2-D grid in factorisation scale and x, read with
+// linear interpolation).  With a dynamic scale mu (= H_T of the event, Sec. 4) the weight
+// takes alpha_s(mu)^(n-2) f(x1, mu) f(x2, mu) instead of alpha_s^(n-2) f(x1) f(x2).  The
+// grids hold alpha_s at nodes uniform in ln mu and ln f at nodes uniform in (ln mu, y) with
+// y = ln(x / (1 - x)), in which ln f is smooth at both ends of x; a point between nodes
+// takes the linear (1-D) or bilinear (2-D) interpolation of the node values, evaluated in
+// FP64 as written; scales and x outside the grids take the edge values.
+// ----------------------------------------------------------------------------------------
+constexpr int kAlphaNodes = 512;
+constexpr int kGridMuNodes = 64;
+constexpr int kGridYNodes = 1024;
+constexpr double kGridMuLo = 5.0, kGridMuHi = 20000.0;  // GeV
+constexpr double kGridXLo = 1e-6, kGridXHi = 1.0 - 1e-9;
+
+struct ScaleGrid {
+  const double* alpha;  // [kAlphaNodes]
+  const double* lnf;    // [kGridMuNodes][kGridYNodes]
+  double lmu_lo, dlmu_alpha, dlmu_pdf, y_lo, dy;
+};
+
+// node index and fraction of v on a uniform grid of n nodes from lo with spacing h
+__host__ __device__ inline int grid_cell(double v, double lo, double h, int n, double& t) {
+#pragma clang fp contract(off)
+  double s = (v - lo) / h;
+  s = s < 0.0 ? 0.0 : (s > (double)(n - 1) ? (double)(n - 1) : s);
+  int i = (int)s;
+  i = i > n - 2 ? n - 2 : i;
+  t = s - (double)i;
+  return i;
+}
+
+__host__ __device__ inline double grid_alpha(const ScaleGrid& g, double lmu) {
+#pragma clang fp contract(off)
+  double t;
+  const int i = grid_cell(lmu, g.lmu_lo, g.dlmu_alpha, kAlphaNodes, t);
+  return (1.0 - t) * g.alpha[i] + t * g.alpha[i + 1];
+}
+
+__host__ __device__ inline double grid_lnf(const ScaleGrid& g, double lmu, double y) {
+#pragma clang fp contract(off)
+  double tm, ty;
+  const int im = grid_cell(lmu, g.lmu_lo, g.dlmu_pdf, kGridMuNodes, tm);
+  const int iy = grid_cell(y, g.y_lo, g.dy, kGridYNodes, ty);
+  const double* r0 = g.lnf + (size_t)im * kGridYNodes + iy;
+  const double* r1 = r0 + kGridYNodes;
+  const double f0 = (1.0 - ty) * r0[0] + ty * r0[1];
+  const double f1 = (1.0 - ty) * r1[0] + ty * r1[1];
+  return (1.0 - tm) * f0 + tm * f1;
+}
+
+// ----------------------------------------------------------------------------------------
 // RAMBO (Sec. 3).  From (rho1..rho4): c = 2 rho1 - 1, phi = 2 pi rho2, q0 = -ln(rho3 rho4),
 // q = q0 (sin cos phi, sin sin phi, c).  Then the conformal map with Q = sum q.
 // ----------------------------------------------------------------------------------------

@@ -3,12 +3,14 @@
 //   BG_KIND 0 generate, 1 amp2, 2 gradient;  BG_N 4..12;  BG_PREC 32 or 64;
 //   BG_FORM 1 one event per lane (for generation of the table classes: the split form),
 //           2 two lanes per event (kinds 0 and 1 only),
-//           3 one event per lane with real polarisations (kind 0 only).
+//           3 one event per lane with real polarisations (kind 0 only),
+//           4 the W-tensor form, 16 lanes per event (kinds 0 and 1).
 // One kernel per translation unit keeps every unit small enough to compile in parallel.
 #include "bg_adjoint.hpp"
 #include "bg_kernels.hpp"
 #include "bg_launch.hpp"
 #include "bg_split.hpp"
+#include "bg_wtensor.hpp"
 
 #if !defined(BG_N) || !defined(BG_PREC) || !defined(BG_KIND) || !defined(BG_FORM)
 #error "BG_N, BG_PREC, BG_KIND and BG_FORM must be defined"
@@ -26,7 +28,8 @@ using Real = double;
 #endif
 
 static_assert(BG_KIND == 2 || (BG_FORM == 1 && has_one_lane(BG_N, BG_PREC)) ||
-                  (BG_FORM == 2 && has_lane_pairs(BG_N, BG_PREC)) || (BG_FORM == 3 && has_real_pol(BG_N, BG_PREC)),
+                  (BG_FORM == 2 && has_lane_pairs(BG_N, BG_PREC)) || (BG_FORM == 3 && has_real_pol(BG_N, BG_PREC)) ||
+                  (BG_FORM == 4 && has_wtensor(BG_N, BG_PREC)),
               "this lane form is not built for (n, prec)");
 
 // Launchers take the workgroup size chosen by the host (which also sizes the partials:
@@ -58,6 +61,21 @@ hipError_t BG_NAME(launch_generate_real_n, BG_N, BG_PREC, BG_KIND)(const GenClas
                      C, W.partials);
   return hipGetLastError();
 #endif
+}
+#elif BG_KIND == 0 && BG_FORM == 4
+hipError_t BG_NAME(launch_generate_w_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
+                                                                hipStream_t s) {
+  (void)block;
+  return launch_generate_w<BG_N, Real>(C, W, s);
+}
+#elif BG_KIND == 1 && BG_FORM == 4
+hipError_t BG_NAME(launch_amp2_w_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
+                                                            const uint8_t* order, double* out, int block,
+                                                            hipStream_t s) {
+  (void)block;
+  hipLaunchKernelGGL((k_amp2_w<BG_N, Real>), dim3((unsigned)((count + 3) / 4)), dim3(64), (w_lds_bytes<BG_N, Real>()),
+                     s, count, mom, hel, order, out);
+  return hipGetLastError();
 }
 #elif BG_KIND == 0 && BG_FORM == 2
 hipError_t BG_NAME(launch_generate2_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,

@@ -571,21 +571,39 @@ __device__ __forceinline__ void block_reduce_store(CSum w, CSum w2, double* dst)
 // 0 times a product), and the per-event outputs of |A|^2, the weight, the cut flag and the
 // log integrand weight; returns w.  Shared by every generation kernel, so that each
 // output rounds identically whichever kernel evaluates the event.
+// Dynamic scale mu = H_T: alpha_s(mu)^(n-2) f(x1, mu) f(x2, mu) over the factors at mu0 that
+// wconst and the sampling density hold (exactly 1 with a fixed scale).
+template <int N>
+__device__ __forceinline__ double scale_ratio(const GenClass& C, double ht, double x1, double x2) {
+#pragma clang fp contract(off)
+  if (!C.dynamic_scale) return 1.0;
+  const double lmu = log(ht);
+  double lr = double(N - 2) * (log(grid_alpha(C.grid, lmu)) - C.log_alpha0);
+  if (C.use_pdf) {
+    const double l1 = log(x1), l2 = log(x2), m1 = log1p(-x1), m2 = log1p(-x2);
+    lr += (grid_lnf(C.grid, lmu, l1 - m1) - (C.pdf.a * l1 + double(C.pdf.b) * m1)) +
+          (grid_lnf(C.grid, lmu, l2 - m2) - (C.pdf.a * l2 + double(C.pdf.b) * m2));
+  }
+  return exp(lr);
+}
+
+// r: scale_ratio of the event.
 template <int N>
 __device__ __forceinline__ double finish_event(const GenClass& C, int64_t i, bool pass, double a2, double shat,
-                                               double x1, double x2) {
+                                               double x1, double x2, double r) {
 #pragma clang fp contract(off)
   double sp = 1.0;
 #pragma unroll
   for (int k = 0; k < (N > 5 ? N - 5 : 5 - N); ++k) sp *= shat;
   if (N < 5) sp = 1.0 / sp;
-  const double w = pass ? C.wconst * sp * a2 : 0.0;
+  const double w = pass ? C.wconst * sp * a2 * r : 0.0;
   if (C.out.weight) C.out.weight[i] = w;
   if (C.out.amp2) C.out.amp2[i] = a2;
   if (C.out.pass) C.out.pass[i] = pass ? 1 : 0;
   if (C.out.logw) {
     double lw = log(a2) + double(N - 5) * log(shat) + C.log_const;
     if (C.use_pdf) lw += C.pdf.a * (log(x1) + log(x2)) + double(C.pdf.b) * (log1p(-x1) + log1p(-x2));
+    if (C.dynamic_scale) lw += log(r);
     C.out.logw[i] = a2 > 0.0 ? lw : -INFINITY;
   }
   return w;
@@ -626,7 +644,7 @@ __device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, Per
     C.out.obs[2 * i] = ht;
     C.out.obs[2 * i + 1] = rmin;
   }
-  return finish_event<N>(C, i, pass, a2, ev.shat, ev.x1, ev.x2);
+  return finish_event<N>(C, i, pass, a2, ev.shat, ev.x1, ev.x2, scale_ratio<N>(C, ht, ev.x1, ev.x2));
 }
 
 // Single-class generation of a class without the span table (FP32 n = 9, FP64 n <= 6): one

@@ -22,7 +22,7 @@ constexpr bool lds_span_table(int n, int prec) { return prec == 32 && n <= 8; }
 // The table classes generate events in two kernels (kinematics at several waves per SIMD,
 // then the recursion at one), joined by a staging buffer of split_words(n) doubles per event.
 constexpr bool split_form(int n, int prec) { return lds_span_table(n, prec); }
-constexpr int split_words(int n) { return 4 * n + 5; }
+constexpr int split_words(int n) { return 4 * (n - 1) + 6; }
 
 // Lane forms the library holds per (n, prec): one event per lane where the recursion fits a
 // lane's 512 registers (FP32 n <= 9, FP64 n <= 6), two lanes per event from FP32 n = 9 and
@@ -35,6 +35,10 @@ constexpr int default_lanes(int n, int prec) { return prec == 32 ? (n >= 10 ? 2 
 // Classes built with real polarisations (real currents: half the registers of complex ones,
 // so one lane per event fits every FP32 class).
 constexpr bool has_real_pol(int n, int prec) { return prec == 32 ? n <= 12 : n <= 8; }
+
+// Classes built with the W-tensor form of the recursion (Eqs. 3.3-3.4), an alternative for
+// large n chosen per class (bg_set_form); FP64 at n = 6 and 10 for parity with the oracle.
+constexpr bool has_wtensor(int n, int prec) { return prec == 32 ? (n == 8 || n >= 10) : (n == 6 || n == 10); }
 
 // The gradient kernel with an event on two lanes (forward values staged in LDS, which
 // bounds it to FP32 n <= 8); elsewhere one lane per event.
@@ -78,6 +82,8 @@ struct Launchers {
   GenerateFn generate2;  // two lanes per event (where has_lane_pairs)
   Amp2Fn amp2_2;
   GenerateFn generate_real;  // real polarisations, one lane per event (where has_real_pol)
+  GenerateFn generate_w;     // W-tensor form, 16 lanes per event (where has_wtensor)
+  Amp2Fn amp2_w;
 };
 
 // Fixed-order compensated reduction of nparts partials into acc, through level2

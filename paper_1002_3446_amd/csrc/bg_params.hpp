@@ -28,11 +28,15 @@ struct GenClass {
   uint32_t key0, key1;
   int32_t use_pdf, random_order;
   int32_t polarisation;       // 0 helicity states, 1 random real unit vectors
+  int32_t dynamic_scale;      // 1: mu = H_T, alpha_s(mu) and f(x, mu) from the grids
+  double lmu0;                // ln of the reference scale (alpha_s, f(x) hold there)
+  double log_alpha0;          // ln alpha_s(mu0)
   double sqrt_s;              // collider sqrt(S), or the fixed sqrt(s_hat) without PDF
   double pt_min, eta_max, dr_min;
   double wconst;              // event-independent weight factor (pb GeV^(2(5-n)))
   double log_const;           // log of the event-independent factors of w_int
   PdfParams pdf;
+  ScaleGrid grid;
   const double* in_u;
   const double* in_x;
   const uint32_t* in_hel;

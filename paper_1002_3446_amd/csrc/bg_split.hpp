@@ -17,13 +17,15 @@ namespace bgk {
 
 // Staging layout: events in tiles of 64 (one wave), each tile holding its words one after
 // another, word w of event j at buf[((j / 64) * kWords + w) * 64 + j % 64], so that a wave
-// reads one contiguous block.  Words: 4N momenta (position t, component mu at 4 t + mu),
-// s_hat, x1, x2, the helicity word with the cut flag at bit 32, and the leg positions
-// (4 bits each).
+// reads one contiguous block.  Words: the centre-of-mass momenta of recursion positions
+// 1..N-1 (position t, component mu at 4 (t - 1) + mu; position 0 is always the beam leg 0,
+// which follows from s_hat), s_hat, x1, x2, the weight factor of the dynamic scale
+// (scale_ratio, 1 with a fixed scale), the helicity word with the cut flag at bit 32, and the
+// leg positions (4 bits each).
 template <int N>
 struct SplitLayout {
-  static constexpr int kMom = 0, kShat = 4 * N, kX1 = 4 * N + 1, kX2 = 4 * N + 2, kMeta = 4 * N + 3,
-                       kLegs = 4 * N + 4, kWords = 4 * N + 5;
+  static constexpr int kMom = 0, kShat = 4 * (N - 1), kX1 = kShat + 1, kX2 = kShat + 2, kR = kShat + 3,
+                       kMeta = kShat + 4, kLegs = kShat + 5, kWords = kShat + 6;
   static_assert(kWords == split_words(N), "staging words");
   __device__ static int64_t at(int64_t j, int w) { return ((j >> 6) * kWords + w) * 64 + (j & 63); }
 };
@@ -44,12 +46,13 @@ __device__ __forceinline__ void kin_one(const GenClass& C, int64_t i, int64_t j,
     C.out.obs[2 * i + 1] = rmin;
   }
 #pragma unroll
-  for (int t = 0; t < N; ++t)
+  for (int t = 1; t < N; ++t)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) buf[L::at(j, L::kMom + 4 * t + mu)] = ev.pc[t][mu];
+    for (int mu = 0; mu < 4; ++mu) buf[L::at(j, L::kMom + 4 * (t - 1) + mu)] = ev.pc[t][mu];
   buf[L::at(j, L::kShat)] = ev.shat;
   buf[L::at(j, L::kX1)] = ev.x1;
   buf[L::at(j, L::kX2)] = ev.x2;
+  buf[L::at(j, L::kR)] = scale_ratio<N>(C, ht, ev.x1, ev.x2);
   uint64_t legs = 0;
 #pragma unroll
   for (int t = 0; t < N; ++t) legs |= (uint64_t)(ev.leg[t] & 15u) << (4 * t);
@@ -64,17 +67,24 @@ template <int N, int POL = 0>
 __device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t j, const double* __restrict__ buf,
                                           LdsTable<N>* tab) {
   using L = SplitLayout<N>;
-  double pc[N][4];
-  uint32_t leg[N];
-#pragma unroll
-  for (int t = 0; t < N; ++t)
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) pc[t][mu] = buf[L::at(j, L::kMom + 4 * t + mu)];
   const double shat = buf[L::at(j, L::kShat)];
+  double pc[N][4];
+  // position 0: the beam leg 0, as build_event forms it
+  const double hb = 0.5 * (C.use_pdf ? sqrt(shat) : C.sqrt_s);
+  pc[0][0] = hb;
+  pc[0][1] = 0.0;
+  pc[0][2] = 0.0;
+  pc[0][3] = hb;
+#pragma unroll
+  for (int t = 1; t < N; ++t)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) pc[t][mu] = buf[L::at(j, L::kMom + 4 * (t - 1) + mu)];
   const double x1 = buf[L::at(j, L::kX1)];
   const double x2 = buf[L::at(j, L::kX2)];
+  const double r = buf[L::at(j, L::kR)];
   const uint64_t meta = (uint64_t)__double_as_longlong(buf[L::at(j, L::kMeta)]);
   const uint64_t legs = (uint64_t)__double_as_longlong(buf[L::at(j, L::kLegs)]);
+  uint32_t leg[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) leg[t] = (uint32_t)(legs >> (4 * t)) & 15u;
   const uint32_t hel = (uint32_t)meta;
@@ -87,7 +97,7 @@ __device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t 
   } else {
     a2 = ordered_amp2<N, float, true>(pc, leg, hel, tab);
   }
-  return finish_event<N>(C, i, pass, a2, shat, x1, x2);
+  return finish_event<N>(C, i, pass, a2, shat, x1, x2, r);
 }
 
 // Launch: blockDim.x = kKinBlock, perm_lds_bytes(N, kKinBlock) bytes of dynamic LDS,

@@ -31,7 +31,8 @@ def oracle_cfg(c):
     return event.config(n=c.n, sqrt_s=c.sqrt_s, use_pdf=c.use_pdf, pdf_a=c.pdf_a, pdf_b=c.pdf_b,
                         tau_min=c.tau_min, alpha_s=c.alpha_s, pt_min=c.pt_min, eta_max=c.eta_max,
                         dr_min=c.dr_min, random_order=c.random_order, seed=c.seed, first_event=c.first_event,
-                        polarisation=c.polarisation)
+                        polarisation=c.polarisation, dynamic_scale=c.dynamic_scale, mu0=c.mu0, pdf_da=c.pdf_da,
+                        pdf_db=c.pdf_db)
 
 
 def to_np(res):
