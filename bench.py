@@ -157,12 +157,11 @@ def mixed_rate(bg, torch):
                                              for i, n in enumerate(ns) if i > 0}}
 
 
-def adjoint_rate(bg, torch, N=1 << 20, steps=5):
-    """Forward + backward of log w_int through the torch Function (gg -> 6g, FP32), on
-    phase-space points the GPU draws first (untimed)."""
+def adjoint_rate(bg, torch, N=1 << 20, steps=5, n=8, prec=32):
+    """Forward + backward of log w_int through the torch Function (gg -> 6g, FP32, unless
+    n and prec say otherwise), on phase-space points the GPU draws first (untimed)."""
     from paper_1002_3446_amd.autograd import log_weight
-    n = 8
-    cfg = bg.config(n, prec=32, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000004)
+    cfg = bg.config(n, prec=prec, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000004)
     d = bg.generate(cfg, N, outputs=("uniforms", "x12", "hel", "order"))
     u = d["uniforms"].requires_grad_(True)
     x = d["x12"].requires_grad_(True)
@@ -180,7 +179,8 @@ def adjoint_rate(bg, torch, N=1 << 20, steps=5):
             evs.append((a, b))
     torch.cuda.synchronize()
     ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
-    return {"n8_fwd_adjoint_fp32_events_per_s": N / (ms * 1e-3), "n8_fwd_adjoint_ms_per_2^20": ms}
+    tag = f"n{n}_fwd_adjoint_fp{prec}"
+    return {f"{tag}_events_per_s": N / (ms * 1e-3), f"{tag}_ms_per_2^{N.bit_length() - 1}": ms}
 
 
 def recursion_rate(bg, torch, n=8, N=1 << 22, reps=5):
@@ -439,7 +439,8 @@ def main():
     if n <= 8 and a.prec == 32:
         kname = f"k_kin<{n}>+k_rec<{n}>"
     else:
-        kname = (f"k_generate<{n},{real_t}>" if bg.get_lanes(n, a.prec) == 1 else f"k_generate_g<{n},{real_t},2>")
+        lanes = bg.get_lanes(n, a.prec)
+        kname = (f"k_generate<{n},{real_t}>" if lanes == 1 else f"k_generate_g<{n},{real_t},{lanes}>")
     achieved = fp * N / (launch_ms * 1e-3)
     line = {
         "metric": f"events/s at gg->{n - 2}g (n={n}) FP{a.prec} recursion (FP64 kinematics and weights), full generation path",
@@ -531,6 +532,8 @@ def main():
         line["recursion_kernel"] = recursion_rate(bg, torch)
         extras.update(hist_rate(bg, torch, out, N))
         extras.update(adjoint_rate(bg, torch))
+        extras.update(adjoint_rate(bg, torch, N=1 << 18, steps=2, n=12, prec=32))
+        extras.update(adjoint_rate(bg, torch, N=1 << 18, steps=2, n=12, prec=64))
         extras.update(mixed_rate(bg, torch))
         line["extras"] = extras
 

@@ -118,7 +118,7 @@ typedef struct {
 } bg_outputs;
 
 /* Generate events of ncfg classes (Sec. 3).  One class: FP32 classes with n <= 8 run as a
- * kinematics kernel and a recursion kernel joined by a staging buffer ((4n + 5) * 8 B per
+ * kinematics kernel and a recursion kernel joined by a staging buffer ((4n + 2) * 8 B per
  * event, chunks of at most 2^21 events); the others as one kernel per call (after a small
  * setup launch, once per density and device, that tabulates the inverse CDF of the parton
  * density when x1, x2 are sampled).  Several classes (mixed multiplicities): as chosen by
@@ -171,7 +171,10 @@ int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
  * gout [N] (dL/dlog w, may be NULL = all ones); grad_u [N][4(n-2)], grad_x [N][2]
  * (zeros when use_pdf = 0) receive gout * d log w_int; logw [N] optional.
  * Events with |A|^2 = 0 get log w = -inf and zero gradients.
- * Supported for n = 4..8 (BG_ENOTSUP for n = 9..12, and for real polarisations). */
+ * Supported for n = 4..12 in both precisions.  The recursion's reverse sweep runs one lane
+ * per event for FP32 n <= 5 and FP64 n = 4, else four lanes per event (each holding one
+ * Lorentz component of every current and of its adjoint).  BG_ENOTSUP for real
+ * polarisations and the dynamic scale. */
 int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const double *x12,
                  const uint32_t *hel, const uint8_t *order, const double *gout,
                  double *grad_u, double *grad_x, double *logw, void *stream);
@@ -224,13 +227,14 @@ int bg_set_launch(int n, int prec, int block, int tile_iters);
 int bg_get_launch(int n, int prec, int *block, int *tile_iters);
 
 /* Lanes of a wave that share one event in the single-class kernels of (n, prec) (bg_generate
- * and bg_amp2; bg_amp2_grad uses two for the recursion adjoint of FP32 n = 6..8 and one
- * otherwise, independent of this): 1 where the library holds the one-lane form (FP32
- * n <= 9, FP64 n <= 6), 2 where it holds the two-lane form (FP32 n >= 9, FP64 n >= 6), else
- * BG_ENOTSUP; 0 restores the default (2 for FP32 n >= 10 and FP64 n >= 7, else 1).  With
- * two lanes each holds two of the four Lorentz components of every current: half the
- * registers, at the price of cross-lane sums in every Minkowski product.  Affects speed
- * only: |A|^2 agrees to the recursion precision's rounding between the forms. */
+ * and bg_amp2; bg_amp2_grad chooses its own, see there): 1 where the library holds the
+ * one-lane form (FP32 n <= 9, FP64 n <= 6), 2 where it holds the two-lane form (FP32 n >= 9,
+ * FP64 n >= 6), 4 where it holds the four-lane form (FP64 n >= 10), else BG_ENOTSUP; other
+ * values BG_EINVAL; 0 restores the default (4 for FP64 n >= 10, 2 for FP32 n >= 10 and
+ * FP64 n = 7..9, else 1).  With G lanes each holds 4/G of the four
+ * Lorentz components of every current: 1/G of the registers, at the price of cross-lane
+ * sums in every Minkowski product.  Affects speed only: |A|^2 agrees to the recursion
+ * precision's rounding between the forms. */
 int bg_set_lanes(int n, int prec, int lanes);
 int bg_get_lanes(int n, int prec, int *lanes);
 

@@ -48,7 +48,9 @@ def mixed_workload(prec, scale=0):
 
 def lane_forms(n, prec):
     """Lanes-per-event forms the library holds for (n, prec)."""
-    return (1, 2) if (prec == 32 and n >= 9) or (prec == 64 and n >= 6) else (1,)
+    grouped = (prec == 32 and n >= 9) or (prec == 64 and n >= 6)
+    one = (prec == 32 and n <= 9) or (prec == 64 and n <= 6)
+    return ((1,) if one else ()) + ((2,) if grouped else ()) + ((4,) if prec == 64 and n >= 10 else ())
 
 
 def wtensor_forms(n, prec):
@@ -65,11 +67,12 @@ def tune_single(prec=32, scale=0, log=print):
         out = bg.generate(cfg, N, outputs=("weight", "acc"))
         cands = [(lanes, 0, block) for lanes in lane_forms(n, prec) for block in (64, 128, 256)]
         if wtensor_forms(n, prec):
-            cands.append((1, 1, 64))   # the W-tensor kernels take fixed 64-lane workgroups
+            cands.append((0, 1, 64))   # W-tensor: fixed 64-lane workgroups, lanes unused
         best = None
         for lanes, form, block in cands:
             bg.set_form(n, prec, form)
-            bg.set_lanes(n, prec, lanes)
+            if lanes:
+                bg.set_lanes(n, prec, lanes)
             bg.set_launch(n, prec, block, bg.get_launch(n, prec)[1] or 1)
             t = _time(lambda: bg.generate(cfg, N, outputs=("weight", "acc"), out_tensors=[out]))
             log(f"n={n} prec={prec} form={form} lanes={lanes} block={block}: {t:.3f} ms for {N} events")
@@ -77,7 +80,8 @@ def tune_single(prec=32, scale=0, log=print):
                 best = (t, block, lanes, form)
         shapes[n] = [best[1], bg.get_launch(n, prec)[1], best[2], best[3]]
         bg.set_launch(n, prec, shapes[n][0], shapes[n][1])
-        bg.set_lanes(n, prec, shapes[n][2])
+        if shapes[n][2]:
+            bg.set_lanes(n, prec, shapes[n][2])
         bg.set_form(n, prec, shapes[n][3])
     return shapes
 

@@ -332,7 +332,7 @@ def get_launch(n: int, prec: int):
 
 
 def set_lanes(n: int, prec: int, lanes: int):
-    """Lanes per event of the single-class kernels of (n, prec): 1, 2 or 0 (default)."""
+    """Lanes per event of the single-class kernels of (n, prec): 1, 2, 4 or 0 (default)."""
     _check("bg_set_lanes", _lib.bg_set_lanes(n, prec, lanes))
 
 

@@ -54,8 +54,6 @@ def _compile(src: str, obj: str, defines: list[str]) -> tuple[str, float]:
 
 
 KINDS = (0, 1, 2)  # 0 generate, 1 amp2, 2 gradient
-GRAD_MAX_N = 8     # beyond, the fully unrolled one-lane adjoint spills kilobytes per lane and takes
-                   # most of the build time
 
 
 def has_one_lane(n: int, p: int) -> bool:
@@ -64,6 +62,10 @@ def has_one_lane(n: int, p: int) -> bool:
 
 def has_lane_pairs(n: int, p: int) -> bool:
     return n >= 9 if p == 32 else n >= 6
+
+
+def has_lane_quads(n: int, p: int) -> bool:
+    return p == 64 and n >= 10
 
 
 def has_real_pol(n: int, p: int) -> bool:
@@ -86,13 +88,12 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
         for p in precs:
             for k in kinds:
                 if k == 2:
-                    if n > GRAD_MAX_N:
-                        continue
                     forms = (1,)
                 else:
                     forms = tuple(f for f, ok in ((1, has_one_lane(n, p)), (2, has_lane_pairs(n, p)),
                                                   (3, k == 0 and has_real_pol(n, p)),
-                                                  (4, has_wtensor(n, p))) if ok)
+                                                  (4, has_wtensor(n, p)),
+                                                  (5, k < 2 and has_lane_quads(n, p))) if ok)
                 for f in forms:
                     obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}_f{f}.o")
                     cost = n ** 3 * (2 if p == 64 else 1) * (4 if k == 2 else 1)

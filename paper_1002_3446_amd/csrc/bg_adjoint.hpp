@@ -512,20 +512,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   o[(GradRaw<N>::words - 1) * G.count] = 1.0;
 }
 
-// LDS words per lane that hold the forward values of the two-lane gradient kernel: currents
-// 4 words each, span scalars 2 (spans of two or more legs), the closure's bracket 4.
-template <int N>
-struct GradStage {
-  static constexpr int slots = Spans<N - 1>::count * 4 + (Spans<N - 1>::count - (N - 1)) * 2 + 4;
-};
+// Whether the gradient kernel keeps its span scalars distributed over the lanes of a group:
+// it holds the currents and their adjoints (twice the forward's registers).
+template <int L, int G, typename T>
+constexpr bool grad_dist_scalars() {
+  return G > 1 && Spans<L>::count * 4 * (4 / G) * (int)(sizeof(T) / 4) > 160;
+}
 
-// Two lanes per event (the grouped recursion and its reverse sweep, bg_group_adj.hpp); both
-// lanes evaluate the kinematics and the momentum adjoints, lane 0 writes.  FP32 with n <= 8
-// (the forward values are staged in LDS, 632 B per lane at n = 8), workgroups of 256 lanes.
-template <int N, typename T>
+// GL lanes per event (the grouped recursion and its reverse sweep, bg_group_adj.hpp); every
+// lane evaluates the kinematics, lane g writes its components of the raw adjoints.  The
+// forward values pass an optimisation barrier before the sweep, so the compiler does not keep
+// the forward pass's intermediates live across it.  Workgroups of 256 lanes.
+template <int N, typename T, int GL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_grad_g(GradArgs G) {
-  constexpr int L = N - 1, GL = 2, C = 2;
+  constexpr int L = N - 1, C = 4 / GL;
   using SP = Spans<L>;
+  using SS = SpanScalars<L, GL, T, grad_dist_scalars<L, GL, T>()>;
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL;
   const int g = (int)(threadIdx.x % GL);
   if (i >= G.count) return;
@@ -555,11 +557,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       e0.im[c] = ls.pick(e.im, c);
     }
   }
-  SpanKGroup<L, GL, T> ks{k, lsd.sg};
+  SpanKGroup<L, GL, T, true> ks{k, lsd.sg};
   cvl<T, C> J[SP::count];
-  T Sr[SP::count], Si[SP::count];
+  SS S(g);
   cvl<T, C> V;
-  bg_forward_g<L, GL, T>(ls, ks, src, J, Sr, Si, V);
+  bg_forward_g<L, GL, T>(ls, ks, src, J, S, V);
   T mr, mi;
   cdot_g<GL>(ls, e0, V, mr, mi);
   const double m2 = double(mr) * double(mr) + double(mi) * double(mi);
@@ -567,60 +569,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (g == 0) G.pbuf[(GradRaw<N>::words - 1) * G.count + i] = 0.0;  // nothing for the second kernel
     return;
   }
-  // The forward values go through LDS (each lane its own slots, [slot][lane]): reloaded
-  // there, they start the reverse sweep as fresh values, so the compiler does not keep the
-  // forward pass's intermediates live across the sweep.
-  {
-    __shared__ float stage[GradStage<N>::slots * 256];
-    volatile float* st = stage + threadIdx.x;
-    int o = 0;
-    static_for<0, SP::count>([&](auto sc) {
-      constexpr int q = decltype(sc)::value;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        st[256 * o++] = J[q].re[c];
-        st[256 * o++] = J[q].im[c];
-      }
-      if constexpr (q >= L) {
-        st[256 * o++] = Sr[q];
-        st[256 * o++] = Si[q];
-      }
-    });
+  static_for<0, SP::count>([&](auto sc) {
+    constexpr int q = decltype(sc)::value;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      st[256 * o++] = V.re[c];
-      st[256 * o++] = V.im[c];
+      opaque(J[q].re[c]);
+      opaque(J[q].im[c]);
     }
-    o = 0;
-    static_for<0, SP::count>([&](auto sc) {
-      constexpr int q = decltype(sc)::value;
+  });
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        J[q].re[c] = st[256 * o++];
-        J[q].im[c] = st[256 * o++];
-      }
-      if constexpr (q >= L) {
-        Sr[q] = st[256 * o++];
-        Si[q] = st[256 * o++];
-      }
-    });
+  for (int m = 0; m < SS::kSlots; ++m) {
+    opaque(S.re[m]);
+    opaque(S.im[m]);
+  }
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      V.re[c] = st[256 * o++];
-      V.im[c] = st[256 * o++];
-    }
+  for (int c = 0; c < C; ++c) {
+    opaque(V.re[c]);
+    opaque(V.im[c]);
   }
   cvl<T, C> srcb[L], e0b;
   T kb[L][C];
-  bg_reverse_g<L, GL, T>(ls, ks, J, Sr, Si, e0, V, T(2.0 * double(mr) / m2), T(2.0 * double(mi) / m2), srcb, e0b,
-                         kb);
+  bg_reverse_g<L, GL, T>(ls, ks, J, S, e0, V, T(2.0 * double(mr) / m2), T(2.0 * double(mi) / m2), srcb, e0b, kb);
   // this lane's components of the raw adjoints (contravariant momentum adjoints)
   double* o = G.pbuf + i;
 #pragma unroll
   for (int t = 1; t < N; ++t) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int mu = 2 * g + c;
+      const int mu = g * C + c;
       o[GradRaw<N>::at(t, mu) * G.count] = double(ls.sg[c] * kb[t - 1][c]);
       o[GradRaw<N>::at(t, 4 + mu) * G.count] = double(srcb[t - 1].re[c]);
       o[GradRaw<N>::at(t, 8 + mu) * G.count] = double(srcb[t - 1].im[c]);

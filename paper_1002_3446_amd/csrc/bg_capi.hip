@@ -24,6 +24,10 @@
                                                                      hipStream_t);                        \
   __attribute__((weak)) hipError_t launch_amp2_2_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*, \
                                                                   const uint8_t*, double*, int, hipStream_t); \
+  __attribute__((weak)) hipError_t launch_generate4_n##N##_p##P##_k0(const GenClass&, const GenWork&, int, \
+                                                                     hipStream_t);                        \
+  __attribute__((weak)) hipError_t launch_amp2_4_n##N##_p##P##_k1(int64_t, const double*, const uint32_t*, \
+                                                                  const uint8_t*, double*, int, hipStream_t); \
   __attribute__((weak)) hipError_t launch_generate_real_n##N##_p##P##_k0(const GenClass&, const GenWork&, int, \
                                                                          hipStream_t); \
   __attribute__((weak)) hipError_t launch_generate_w_n##N##_p##P##_k0(const GenClass&, const GenWork&, int,  \
@@ -46,10 +50,12 @@ using namespace bgk;
 #define BG_ROW(N)                                                                                       \
   {{launch_generate_n##N##_p32_k0, launch_amp2_n##N##_p32_k1, launch_grad_n##N##_p32_k2,                \
     launch_generate2_n##N##_p32_k0, launch_amp2_2_n##N##_p32_k1, launch_generate_real_n##N##_p32_k0,    \
-    launch_generate_w_n##N##_p32_k0, launch_amp2_w_n##N##_p32_k1},                                       \
+    launch_generate_w_n##N##_p32_k0, launch_amp2_w_n##N##_p32_k1, launch_generate4_n##N##_p32_k0,        \
+    launch_amp2_4_n##N##_p32_k1},                                                                        \
    {launch_generate_n##N##_p64_k0, launch_amp2_n##N##_p64_k1, launch_grad_n##N##_p64_k2,                \
     launch_generate2_n##N##_p64_k0, launch_amp2_2_n##N##_p64_k1, launch_generate_real_n##N##_p64_k0,    \
-    launch_generate_w_n##N##_p64_k0, launch_amp2_w_n##N##_p64_k1}}
+    launch_generate_w_n##N##_p64_k0, launch_amp2_w_n##N##_p64_k1, launch_generate4_n##N##_p64_k0,        \
+    launch_amp2_4_n##N##_p64_k1}}
 
 const Launchers* table(int n, int prec) {
   static const Launchers t[9][2] = {BG_ROW(4),  BG_ROW(5),  BG_ROW(6), BG_ROW(7), BG_ROW(8),
@@ -440,7 +446,9 @@ int plan_class(const bg_config& c, const GenClass& G, ClassPlan& P) {
   const Launchers* L = table(c.n, c.prec);
   P.wform = !c.polarisation && form_of(c.n, c.prec) == 1;
   P.lanes = (c.polarisation || P.wform) ? 1 : lanes_of(c.n, c.prec);
-  P.fn = c.polarisation ? L->generate_real : (P.wform ? L->generate_w : (P.lanes == 2 ? L->generate2 : L->generate));
+  P.fn = c.polarisation ? L->generate_real
+                        : (P.wform ? L->generate_w
+                                   : (P.lanes == 4 ? L->generate4 : (P.lanes == 2 ? L->generate2 : L->generate)));
   if (!P.fn) return BG_ENOTSUP;
   P.staged = P.wform || (P.lanes == 1 && split_form(c.n, c.prec));
   P.block = P.staged ? kLdsLanes : shape_of(c.n, c.prec).block;
@@ -670,9 +678,10 @@ int bg_set_launch(int n, int prec, int block, int tile_iters) {
 int bg_set_lanes(int n, int prec, int lanes) {
   const Launchers* L = table(n, prec);
   if (!L) return BG_ENOTSUP;
-  if (lanes != 0 && lanes != 1 && lanes != 2) return BG_EINVAL;
+  if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return BG_EINVAL;
   if (lanes == 1 && !(L->generate && L->amp2)) return BG_ENOTSUP;
   if (lanes == 2 && !(L->generate2 && L->amp2_2)) return BG_ENOTSUP;
+  if (lanes == 4 && !(L->generate4 && L->amp2_4)) return BG_ENOTSUP;
   std::lock_guard<std::mutex> lk(g_shape_mu);
   g_lanes[n][prec == 32 ? 0 : 1] = lanes;
   return BG_OK;
@@ -883,7 +892,8 @@ int bg_amp2(int n, int prec, int64_t N, const double* mom, const uint32_t* hel, 
   const Launchers* L = table(n, prec);
   if (!L) return BG_ENOTSUP;
   if (N < 0) return BG_EINVAL;
-  const Amp2Fn f = form_of(n, prec) == 1 ? L->amp2_w : (lanes_of(n, prec) == 2 ? L->amp2_2 : L->amp2);
+  const int lanes = lanes_of(n, prec);
+  const Amp2Fn f = form_of(n, prec) == 1 ? L->amp2_w : (lanes == 4 ? L->amp2_4 : (lanes == 2 ? L->amp2_2 : L->amp2));
   if (!f) return BG_ENOTSUP;
   if (N == 0) return BG_OK;
   if (!mom || !hel || !order || !amp2_out) return BG_EINVAL;

@@ -448,6 +448,14 @@ __device__ __forceinline__ void span_sum(const double (&k)[L][4], double K[4]) {
   });
 }
 
+// An optimisation barrier on a register value (no code is emitted): after it the compiler
+// knows nothing of x, so it neither merges a computation that starts from x with another nor
+// keeps what produced x live for later uses.
+template <typename T>
+__device__ __forceinline__ void opaque(T& x) {
+  asm volatile("" : "+v"(x));
+}
+
 template <int L>
 struct Spans {
   static constexpr int count = L * (L + 1) / 2;

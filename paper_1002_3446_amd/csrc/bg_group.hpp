@@ -62,13 +62,108 @@ struct LaneShare {
 #pragma unroll
     for (int c = 0; c < C; ++c) sg[c] = (mu0 + c == 0) ? T(1) : T(-1);
   }
-  // the held components of a full four-vector (selects, no dynamic register indexing)
+  // the held components of a full four-vector, without dynamic register indexing: one select
+  // for two lanes; for four, bit masks (a chain of three selects is turned back into a
+  // dynamically indexed array on the stack)
   template <typename U>
   __device__ __forceinline__ U pick(const U (&v)[4], int c) const {
-    U r = v[c];
+    if constexpr (G == 4) {
+      using B = typename std::conditional<sizeof(U) == 8, uint64_t, uint32_t>::type;
+      B r = 0;
 #pragma unroll
-    for (int q = 1; q < G; ++q) r = (mu0 == q * C) ? v[q * C + c] : r;
-    return r;
+      for (int q = 0; q < 4; ++q) r |= __builtin_bit_cast(B, v[q]) & (B)(-(B)(mu0 == q));
+      return __builtin_bit_cast(U, r);
+    } else {
+      U r = v[c];
+#pragma unroll
+      for (int q = 1; q < G; ++q) r = (mu0 == q * C) ? v[q * C + c] : r;
+      return r;
+    }
+  }
+};
+
+// DPP control that gives every lane of a group of G adjacent lanes the value of the group's
+// lane K (a quad permutation: [K, K, K, K] for G = 4, [K, K, 2 + K, 2 + K] for G = 2).
+template <int G, int K>
+constexpr int group_bcast_ctrl() {
+  return G == 4 ? (K | (K << 2) | (K << 4) | (K << 6)) : (K | (K << 2) | ((2 + K) << 4) | ((2 + K) << 6));
+}
+
+template <int G, int K, typename T>
+__device__ __forceinline__ T group_bcast(T x) {
+  if constexpr (G == 1) {
+    return x;
+  } else if constexpr (std::is_same<T, float>::value) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), group_bcast_ctrl<G, K>(),
+                                                              0xF, 0xF, false));
+  } else {
+    return dpp_mov<group_bcast_ctrl<G, K>()>(x);
+  }
+}
+
+// Whether a group keeps its span scalars distributed over its lanes: where the currents of
+// every span already take most of a lane's registers (FP32 n = 12 with two lanes, FP64 from
+// n = 9), replicating the scalars on every lane would spill.
+template <int L, int G, typename T>
+constexpr bool dist_scalars() {
+  return G > 1 && Spans<L>::count * 2 * (4 / G) * (int)(sizeof(T) / 4) > 240;
+}
+
+// The span scalars S of a group (the complex sums of the three-gluon dots, one per span of
+// two or more legs; spans counted from the first of two legs, q = s - L).  Replicated: every
+// lane holds every scalar.  Distributed: lane q % G of the group holds span q in slot q / G,
+// and a read broadcasts it over the group (one DPP move per word); writes of a group-uniform
+// value go to the owning lane by a select.  Either way every lane reads bitwise the value
+// that was written.
+template <int L, int G, typename T, bool DIST = dist_scalars<L, G, T>()>
+struct SpanScalars {
+  static constexpr int kCount = Spans<L>::count - L;
+  static constexpr int kSlots = DIST ? (kCount + G - 1) / G : kCount;
+  T re[kSlots], im[kSlots];
+  int g;  // this lane's place in its group
+  __device__ __forceinline__ explicit SpanScalars(int g_) : g(g_) {}
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) re[m] = im[m] = T(0);
+  }
+  template <int S>
+  __device__ __forceinline__ void get(T& r, T& i) const {
+    constexpr int q = S - L;
+    static_assert(q >= 0 && q < kCount, "span scalar index");
+    if constexpr (DIST) {
+      r = group_bcast<G, q % G>(re[q / G]);
+      i = group_bcast<G, q % G>(im[q / G]);
+    } else {
+      r = re[q];
+      i = im[q];
+    }
+  }
+  template <int S>
+  __device__ __forceinline__ void put(T r, T i) {
+    constexpr int q = S - L;
+    static_assert(q >= 0 && q < kCount, "span scalar index");
+    if constexpr (DIST) {
+      const bool own = g == q % G;
+      re[q / G] = own ? r : re[q / G];
+      im[q / G] = own ? i : im[q / G];
+    } else {
+      re[q] = r;
+      im[q] = i;
+    }
+  }
+  // S -= (r, i) for a group-uniform (r, i)
+  template <int S>
+  __device__ __forceinline__ void sub(T r, T i) {
+    constexpr int q = S - L;
+    static_assert(q >= 0 && q < kCount, "span scalar index");
+    if constexpr (DIST) {
+      const bool own = g == q % G;
+      re[q / G] = own ? re[q / G] - r : re[q / G];
+      im[q / G] = own ? im[q / G] - i : im[q / G];
+    } else {
+      re[q] -= r;
+      im[q] -= i;
+    }
   }
 };
 
@@ -112,15 +207,22 @@ __device__ __forceinline__ void caxpy_l(T cr, T ci, const cvl<T, C>& y, cvl<T, C
 
 // Covariant span momenta of this lane's components, summed left to right in FP64 over the
 // legs and cast to T; propagators 1/K^2 from the group sum of FP64 partials.
-template <int L, int G, typename T>
+template <int L, int G, typename T, bool AFRESH = false>
 struct SpanKGroup {
   static constexpr int C = 4 / G;
   const double (&k)[L][C];   // covariant FP64 leg components held by this lane
   const double (&sg)[C];     // their metric signs
+  // With AFRESH, every use sums afresh: an optimisation barrier on the first term keeps the
+  // compiler from merging the sums of one span over the whole kernel and holding them in
+  // registers (the gradient kernels, which hold currents and adjoints, gain registers; the
+  // forward kernels lose more to the extra FP64 adds than they gain).
   template <int A, int B>
   __device__ __forceinline__ void sum(double d[C]) const {
 #pragma unroll
-    for (int c = 0; c < C; ++c) d[c] = k[A][c];
+    for (int c = 0; c < C; ++c) {
+      d[c] = k[A][c];
+      if constexpr (AFRESH) opaque(d[c]);
+    }
     static_for<A + 1, B + 1>([&](auto t) {
 #pragma unroll
       for (int c = 0; c < C; ++c) d[c] += k[decltype(t)::value][c];
@@ -153,10 +255,9 @@ struct SpanKGroup {
 };
 
 // One span [A..B]: its bracket sum V (contravariant, this lane's components).
-template <int L, int A, int B, int G, typename T, typename KS>
+template <int L, int A, int B, int G, typename T, typename KS, typename SS>
 __device__ __forceinline__ void span_vertex_g(const LaneShare<G, T>& ls, const KS& ks,
-                                              const cvl<T, 4 / G> (&J)[Spans<L>::count],
-                                              const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
+                                              const cvl<T, 4 / G> (&J)[Spans<L>::count], const SS& S,
                                               cvl<T, 4 / G>& V, T& sr, T& si) {
   constexpr int C = 4 / G;
   using SP = Spans<L>;
@@ -197,13 +298,15 @@ __device__ __forceinline__ void span_vertex_g(const LaneShare<G, T>& ls, const K
   });
   static_for<A + 1, B>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
-    constexpr int Sx = SP::at(A, j);
-    caxpy_l(-Sr[Sx], -Si[Sx], J[SP::at(j + 1, B)], Z);
+    T r, i;
+    S.template get<SP::at(A, j)>(r, i);
+    caxpy_l(-r, -i, J[SP::at(j + 1, B)], Z);
   });
   static_for<A, B - 1>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    constexpr int Sx = SP::at(i + 1, B);
-    caxpy_l(-Sr[Sx], -Si[Sx], J[SP::at(A, i)], Z);
+    T r, im;
+    S.template get<SP::at(i + 1, B)>(r, im);
+    caxpy_l(-r, -im, J[SP::at(A, i)], Z);
   });
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -214,11 +317,10 @@ __device__ __forceinline__ void span_vertex_g(const LaneShare<G, T>& ls, const K
 
 // Forward recursion: every stored current and span scalar, and the undivided bracket sum V
 // of the full span (this lane's components).
-template <int L, int G, typename T, typename KS>
+template <int L, int G, typename T, typename KS, typename SS>
 __device__ __forceinline__ void bg_forward_g(const LaneShare<G, T>& ls, const KS& ks,
                                              const cvl<T, 4 / G> (&src)[L], cvl<T, 4 / G> (&J)[Spans<L>::count],
-                                             T (&Sr)[Spans<L>::count], T (&Si)[Spans<L>::count],
-                                             cvl<T, 4 / G>& Vfull) {
+                                             SS& S, cvl<T, 4 / G>& Vfull) {
   constexpr int C = 4 / G;
   using SP = Spans<L>;
   static_for<0, L>([&](auto ac) { J[decltype(ac)::value] = src[decltype(ac)::value]; });
@@ -228,19 +330,18 @@ __device__ __forceinline__ void bg_forward_g(const LaneShare<G, T>& ls, const KS
       constexpr int a = decltype(ac)::value, b = a + len - 1, s = SP::at(a, b);
       cvl<T, C> V;
       T sr, si;
-      span_vertex_g<L, a, b, G, T>(ls, ks, J, Sr, Si, V, sr, si);
+      span_vertex_g<L, a, b, G, T>(ls, ks, J, S, V, sr, si);
       const T prop = ks.template prop<a, b>();
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         J[s].re[c] = V.re[c] * prop;
         J[s].im[c] = V.im[c] * prop;
       }
-      Sr[s] = sr;
-      Si[s] = si;
+      S.template put<s>(sr, si);
     });
   });
   T sr, si;
-  span_vertex_g<L, 0, L - 1, G, T>(ls, ks, J, Sr, Si, Vfull, sr, si);
+  span_vertex_g<L, 0, L - 1, G, T>(ls, ks, J, S, Vfull, sr, si);
 }
 
 // Forward recursion and closure m = eps0 . V[0..L-1] (every lane of the group gets m).
@@ -251,9 +352,9 @@ __device__ __forceinline__ void bg_amplitude_g(const LaneShare<G, T>& ls, const 
   constexpr int C = 4 / G;
   using SP = Spans<L>;
   cvl<T, C> J[SP::count];
-  T Sr[SP::count], Si[SP::count];
+  SpanScalars<L, G, T> S(ls.mu0 / C);
   cvl<T, C> V;
-  bg_forward_g<L, G, T>(ls, ks, src, J, Sr, Si, V);
+  bg_forward_g<L, G, T>(ls, ks, src, J, S, V);
   T mr, mi;
   cdot_g<G>(ls, eps0, V, mr, mi);
   m_re = double(mr);

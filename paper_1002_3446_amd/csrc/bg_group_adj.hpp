@@ -59,13 +59,11 @@ __device__ __forceinline__ void spread_g(const T (&Kb)[C], T (&kb)[L][C]) {
 // Reverse of span_vertex_g for span [A..B]: given Vb (adjoint of the bracket sum, this lane's
 // components) and the adjoint (sbr, sbi) of its span scalar, accumulate into the adjoints of
 // the sub-currents, sub-span scalars and covariant leg momenta.
-template <int L, int A, int B, int G, typename T, typename KS>
+template <int L, int A, int B, int G, typename T, typename KS, typename SS>
 __device__ __forceinline__ void span_vertex_adj_g(const LaneShare<G, T>& ls, const KS& ks,
-                                                  const cvl<T, 4 / G> (&J)[Spans<L>::count],
-                                                  const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
+                                                  const cvl<T, 4 / G> (&J)[Spans<L>::count], const SS& S,
                                                   const cvl<T, 4 / G>& Vb, T sbr, T sbi,
-                                                  cvl<T, 4 / G> (&Jb)[Spans<L>::count], T (&Sbr)[Spans<L>::count],
-                                                  T (&Sbi)[Spans<L>::count], T (&kb)[L][4 / G]) {
+                                                  cvl<T, 4 / G> (&Jb)[Spans<L>::count], SS& Sb, T (&kb)[L][4 / G]) {
   constexpr int C = 4 / G;
   using SP = Spans<L>;
   // V = 2X + sigma Yc + Z
@@ -83,17 +81,19 @@ __device__ __forceinline__ void span_vertex_adj_g(const LaneShare<G, T>& ls, con
     constexpr int j = decltype(jc)::value, Sx = SP::at(A, j), Jx = SP::at(j + 1, B);
     T cr = T(0), ci = T(0);
     conj_dot_g<G>(J[Jx], Zb, cr, ci);
-    Sbr[Sx] -= cr;
-    Sbi[Sx] -= ci;
-    axpy_adj_y(-Sr[Sx], -Si[Sx], Zb, Jb[Jx]);
+    Sb.template sub<Sx>(cr, ci);
+    T sr, si;
+    S.template get<Sx>(sr, si);
+    axpy_adj_y(-sr, -si, Zb, Jb[Jx]);
   });
   static_for<A, B - 1>([&](auto ic) {
     constexpr int i = decltype(ic)::value, Sx = SP::at(i + 1, B), Jx = SP::at(A, i);
     T cr = T(0), ci = T(0);
     conj_dot_g<G>(J[Jx], Zb, cr, ci);
-    Sbr[Sx] -= cr;
-    Sbi[Sx] -= ci;
-    axpy_adj_y(-Sr[Sx], -Si[Sx], Zb, Jb[Jx]);
+    Sb.template sub<Sx>(cr, ci);
+    T sr, si;
+    S.template get<Sx>(sr, si);
+    axpy_adj_y(-sr, -si, Zb, Jb[Jx]);
   });
   // X += (J[A..i] . J[j+1..B]) J[i+1..j]
   static_for<A, B - 1>([&](auto ic) {
@@ -164,21 +164,20 @@ __device__ __forceinline__ void span_vertex_adj_g(const LaneShare<G, T>& ls, con
 // Reverse sweep of bg_forward_g + closure.  mb: adjoint of m = eps0 . V (identical on the
 // lanes of a group).  Outputs the adjoints of the sources (srcb), of the closing polarisation
 // (e0b) and of the scaled covariant leg momenta (kb), this lane's components.
-template <int L, int G, typename T, typename KS>
+template <int L, int G, typename T, typename KS, typename SS>
 __device__ __forceinline__ void bg_reverse_g(const LaneShare<G, T>& ls, const KS& ks,
-                                             const cvl<T, 4 / G> (&J)[Spans<L>::count],
-                                             const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
+                                             const cvl<T, 4 / G> (&J)[Spans<L>::count], const SS& S,
                                              const cvl<T, 4 / G>& eps0, const cvl<T, 4 / G>& Vfull, T mbr, T mbi,
                                              cvl<T, 4 / G> (&srcb)[L], cvl<T, 4 / G>& e0b, T (&kb)[L][4 / G]) {
   constexpr int C = 4 / G;
   using SP = Spans<L>;
   cvl<T, C> Jb[SP::count];
-  T Sbr[SP::count], Sbi[SP::count];
+  SS Sb(S.g);
+  Sb.zero();
   static_for<0, SP::count>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
 #pragma unroll
     for (int c = 0; c < C; ++c) Jb[s].re[c] = Jb[s].im[c] = T(0);
-    Sbr[s] = Sbi[s] = T(0);
   });
   static_for<0, L>([&](auto tc) {
 #pragma unroll
@@ -189,7 +188,7 @@ __device__ __forceinline__ void bg_reverse_g(const LaneShare<G, T>& ls, const KS
   for (int c = 0; c < C; ++c) Vb.re[c] = Vb.im[c] = e0b.re[c] = e0b.im[c] = T(0);
   mdot_adj(ls, eps0, mbr, mbi, Vb);
   mdot_adj(ls, Vfull, mbr, mbi, e0b);
-  span_vertex_adj_g<L, 0, L - 1, G, T>(ls, ks, J, Sr, Si, Vb, T(0), T(0), Jb, Sbr, Sbi, kb);
+  span_vertex_adj_g<L, 0, L - 1, G, T>(ls, ks, J, S, Vb, T(0), T(0), Jb, Sb, kb);
   // lengths L-1 down to 2
   static_for<0, L - 2>([&](auto rc) {
     constexpr int len = L - 1 - decltype(rc)::value;
@@ -212,7 +211,9 @@ __device__ __forceinline__ void bg_reverse_g(const LaneShare<G, T>& ls, const KS
 #pragma unroll
       for (int c = 0; c < C; ++c) Kb[c] = T(-2) * ls.sg[c] * Kc[c] * prop * rj;
       spread_g<a, b, L>(Kb, kb);
-      span_vertex_adj_g<L, a, b, G, T>(ls, ks, J, Sr, Si, Vbs, Sbr[s], Sbi[s], Jb, Sbr, Sbi, kb);
+      T sbr, sbi;
+      Sb.template get<s>(sbr, sbi);
+      span_vertex_adj_g<L, a, b, G, T>(ls, ks, J, S, Vbs, sbr, sbi, Jb, Sb, kb);
     });
   });
   static_for<0, L>([&](auto tc) { srcb[decltype(tc)::value] = Jb[decltype(tc)::value]; });

@@ -4,7 +4,8 @@
 //   BG_FORM 1 one event per lane (for generation of the table classes: the split form),
 //           2 two lanes per event (kinds 0 and 1 only),
 //           3 one event per lane with real polarisations (kind 0 only),
-//           4 the W-tensor form, 16 lanes per event (kinds 0 and 1).
+//           4 the W-tensor form, 16 lanes per event (kinds 0 and 1),
+//           5 four lanes per event (kinds 0 and 1 only).
 // One kernel per translation unit keeps every unit small enough to compile in parallel.
 #include "bg_adjoint.hpp"
 #include "bg_kernels.hpp"
@@ -29,8 +30,11 @@ using Real = double;
 
 static_assert(BG_KIND == 2 || (BG_FORM == 1 && has_one_lane(BG_N, BG_PREC)) ||
                   (BG_FORM == 2 && has_lane_pairs(BG_N, BG_PREC)) || (BG_FORM == 3 && has_real_pol(BG_N, BG_PREC)) ||
-                  (BG_FORM == 4 && has_wtensor(BG_N, BG_PREC)),
+                  (BG_FORM == 4 && has_wtensor(BG_N, BG_PREC)) || (BG_FORM == 5 && has_lane_quads(BG_N, BG_PREC)),
               "this lane form is not built for (n, prec)");
+
+// Lanes per event of the grouped forms
+#define BG_GROUP (BG_FORM == 5 ? 4 : 2)
 
 // Launchers take the workgroup size chosen by the host (which also sizes the partials:
 // one per workgroup, ceil(count * lanes / block) workgroups; the table classes always use
@@ -77,11 +81,16 @@ hipError_t BG_NAME(launch_amp2_w_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const
                      s, count, mom, hel, order, out);
   return hipGetLastError();
 }
-#elif BG_KIND == 0 && BG_FORM == 2
-hipError_t BG_NAME(launch_generate2_n, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
-                                                               hipStream_t s) {
-  const int64_t nb = (2 * C.count + block - 1) / block;
-  hipLaunchKernelGGL((k_generate_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, C, W.partials);
+#elif BG_KIND == 0 && (BG_FORM == 2 || BG_FORM == 5)
+#if BG_FORM == 2
+#define BG_GEN_GROUP launch_generate2_n
+#else
+#define BG_GEN_GROUP launch_generate4_n
+#endif
+hipError_t BG_NAME(BG_GEN_GROUP, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
+                                                         hipStream_t s) {
+  const int64_t nb = (BG_GROUP * C.count + block - 1) / block;
+  hipLaunchKernelGGL((k_generate_g<BG_N, Real, BG_GROUP>), dim3((unsigned)nb), dim3(block), 0, s, C, W.partials);
   return hipGetLastError();
 }
 #elif BG_KIND == 1 && BG_FORM == 1
@@ -93,32 +102,36 @@ hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const d
   hipLaunchKernelGGL((k_amp2<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
   return hipGetLastError();
 }
-#elif BG_KIND == 1 && BG_FORM == 2
-hipError_t BG_NAME(launch_amp2_2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
-                                                            const uint8_t* order, double* out, int block,
-                                                            hipStream_t s) {
-  const int64_t nb = (2 * count + block - 1) / block;
-  hipLaunchKernelGGL((k_amp2_g<BG_N, Real, 2>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order, out);
+#elif BG_KIND == 1 && (BG_FORM == 2 || BG_FORM == 5)
+#if BG_FORM == 2
+#define BG_AMP2_GROUP launch_amp2_2_n
+#else
+#define BG_AMP2_GROUP launch_amp2_4_n
+#endif
+hipError_t BG_NAME(BG_AMP2_GROUP, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
+                                                          const uint8_t* order, double* out, int block,
+                                                          hipStream_t s) {
+  const int64_t nb = (BG_GROUP * count + block - 1) / block;
+  hipLaunchKernelGGL((k_amp2_g<BG_N, Real, BG_GROUP>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order,
+                     out);
   return hipGetLastError();
 }
 #elif BG_KIND == 2
-// Two kernels: the recursion and its reverse sweep (one or two lanes per event), then the
-// helicity-source, momentum, RAMBO and x adjoints (one lane per event).
-#if BG_PREC == 32 && BG_N >= 6 && BG_N <= 8
-#define BG_GRAD_PAIRS 1
-#else
-#define BG_GRAD_PAIRS 0
+// Two kernels: the recursion and its reverse sweep (one, two or four lanes per event), then
+// the helicity-source, momentum, RAMBO and x adjoints (one lane per event).
+#ifndef BG_GRAD_LANES
+#define BG_GRAD_LANES grad_lanes(BG_N, BG_PREC)
 #endif
-static_assert(grad_lane_pairs(BG_N, BG_PREC) == (BG_GRAD_PAIRS == 1), "gradient lane-pair condition");
 hipError_t BG_NAME(launch_grad_n, BG_N, BG_PREC, BG_KIND)(const GradArgs& G, int block, hipStream_t s) {
-#if BG_GRAD_PAIRS
-  (void)block;
-  const int64_t nb = (2 * G.count + 255) / 256;  // 256 lanes: the LDS staging fills a CU
-  hipLaunchKernelGGL((k_grad_g<BG_N, Real>), dim3((unsigned)nb), dim3(256), 0, s, G);
-#else
-  const int64_t nb = (G.count + block - 1) / block;
-  hipLaunchKernelGGL((k_grad<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, G);
-#endif
+  constexpr int GL = BG_GRAD_LANES;
+  if constexpr (GL == 1) {
+    const int64_t nb = (G.count + block - 1) / block;
+    hipLaunchKernelGGL((k_grad<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, G);
+  } else {
+    (void)block;
+    const int64_t nb = (GL * G.count + 255) / 256;
+    hipLaunchKernelGGL((k_grad_g<BG_N, Real, GL>), dim3((unsigned)nb), dim3(256), 0, s, G);
+  }
   hipLaunchKernelGGL((k_grad_back<BG_N>), dim3((unsigned)((G.count + 255) / 256)), dim3(256), 0, s, G);
   return hipGetLastError();
 }

@@ -25,12 +25,15 @@ constexpr bool split_form(int n, int prec) { return lds_span_table(n, prec); }
 constexpr int split_words(int n) { return 4 * (n - 1) + 6; }
 
 // Lane forms the library holds per (n, prec): one event per lane where the recursion fits a
-// lane's 512 registers (FP32 n <= 9, FP64 n <= 6), two lanes per event from FP32 n = 9 and
-// FP64 n = 6 on (the one-lane form spills kilobytes per lane beyond that).  Which form runs
-// is a launch setting (bg_set_lanes), defaulting to default_lanes.
+// lane's 512 registers (FP32 n <= 9, FP64 n <= 6); two lanes per event from FP32 n = 9 and
+// FP64 n = 6 on (the one-lane form spills kilobytes per lane beyond that); four lanes for
+// FP64 n >= 10, where two still spill (FP64 n = 12: 2.9 KB per lane with two, 448 B with
+// four).  Which form runs is a launch
+// setting (bg_set_lanes), defaulting to default_lanes.
 constexpr bool has_one_lane(int n, int prec) { return prec == 32 ? n <= 9 : n <= 6; }
 constexpr bool has_lane_pairs(int n, int prec) { return prec == 32 ? n >= 9 : n >= 6; }
-constexpr int default_lanes(int n, int prec) { return prec == 32 ? (n >= 10 ? 2 : 1) : (n >= 7 ? 2 : 1); }
+constexpr bool has_lane_quads(int n, int prec) { return prec == 64 && n >= 10; }
+constexpr int default_lanes(int n, int prec) { return prec == 32 ? (n >= 10 ? 2 : 1) : (n >= 10 ? 4 : (n >= 7 ? 2 : 1)); }
 
 // Classes built with real polarisations (real currents: half the registers of complex ones,
 // so one lane per event fits every FP32 class).
@@ -42,7 +45,11 @@ constexpr bool has_wtensor(int n, int prec) { return prec == 32 ? (n == 8 || n >
 
 // The gradient kernel with an event on two lanes (forward values staged in LDS, which
 // bounds it to FP32 n <= 8); elsewhere one lane per event.
-constexpr bool grad_lane_pairs(int n, int prec) { return prec == 32 && n >= 6 && n <= 8; }
+// Lanes per event of the gradient's recursion kernel: one (k_grad) for FP32 n <= 5 and
+// FP64 n = 4, else the grouped reverse sweep (k_grad_g) with four lanes, one Lorentz
+// component each: the currents and their adjoints stay in registers through FP32 n = 11
+// and FP64 n = 9.
+constexpr int grad_lanes(int n, int prec) { return prec == 32 ? (n <= 5 ? 1 : 4) : (n <= 4 ? 1 : 4); }
 
 struct GradArgs {
   int64_t count;
@@ -84,6 +91,8 @@ struct Launchers {
   GenerateFn generate_real;  // real polarisations, one lane per event (where has_real_pol)
   GenerateFn generate_w;     // W-tensor form, 16 lanes per event (where has_wtensor)
   Amp2Fn amp2_w;
+  GenerateFn generate4;      // four lanes per event (where has_lane_quads)
+  Amp2Fn amp2_4;
 };
 
 // Fixed-order compensated reduction of nparts partials into acc, through level2

@@ -28,8 +28,9 @@ EPS = 2.0**-52
 
 def lane_forms(n, prec):
     """Lanes-per-event forms the library holds for (n, prec): one lane for FP32 n <= 9 and
-    FP64 n <= 6, two lanes for FP32 n >= 9 and FP64 n >= 6."""
-    return [l for l, ok in ((1, n <= (9 if prec == 32 else 6)), (2, n >= (9 if prec == 32 else 6))) if ok]
+    FP64 n <= 6, two lanes for FP32 n >= 9 and FP64 n >= 6, four for FP64 n >= 10."""
+    return [l for l, ok in ((1, n <= (9 if prec == 32 else 6)), (2, n >= (9 if prec == 32 else 6)),
+                            (4, prec == 64 and n >= 10)) if ok]
 
 
 def popcount(words, n):

@@ -78,7 +78,19 @@ def test_host_error_paths():
     assert lib.bg_set_lanes(8, 32, 0) == bg.BG_OK and lib.bg_set_lanes(12, 32, 0) == bg.BG_OK
     assert lib.bg_get_lanes(8, 32, ctypes.byref(v)) == bg.BG_OK and v.value == 1    # defaults
     assert lib.bg_get_lanes(12, 32, ctypes.byref(v)) == bg.BG_OK and v.value == 2
-    assert lib.bg_set_lanes(8, 32, 2) == bg.BG_ENOTSUP   # no two-lane form at n = 8 FP32
+    assert lib.bg_set_lanes(8, 32, 2) == bg.BG_ENOTSUP   # no grouped form at n = 8 FP32
+    assert lib.bg_set_lanes(8, 32, 4) == bg.BG_ENOTSUP
+    assert lib.bg_set_lanes(12, 32, 4) == bg.BG_ENOTSUP  # four lanes: FP64 n >= 10 only
+    assert lib.bg_set_lanes(9, 64, 4) == bg.BG_ENOTSUP
+    assert lib.bg_set_lanes(12, 64, 1) == bg.BG_ENOTSUP  # no one-lane form at n = 12 FP64
+    assert lib.bg_set_lanes(12, 32, 8) == bg.BG_EINVAL
+    keep64 = bg.get_lanes(12, 64)
+    assert lib.bg_set_lanes(12, 64, 0) == bg.BG_OK
+    assert lib.bg_get_lanes(12, 64, ctypes.byref(v)) == bg.BG_OK and v.value == 4   # default
+    for l in (2, 4):
+        assert lib.bg_set_lanes(12, 64, l) == bg.BG_OK
+        assert lib.bg_get_lanes(12, 64, ctypes.byref(v)) == bg.BG_OK and v.value == l
+    bg.set_lanes(12, 64, keep64)
     for n, l in keep.items():
         bg.set_lanes(n, 32, l)
     b, k = ctypes.c_int(), ctypes.c_int()

@@ -29,7 +29,8 @@ def dev(u, x, hel, order):
             torch.tensor(hel.astype(np.int64), device="cuda").to(torch.int32), torch.tensor(order, device="cuda"))
 
 
-@pytest.mark.parametrize("n,prec", [(5, 64), (8, 64), (8, 32), (6, 32), (7, 32), (4, 64), (4, 32), (6, 64)])
+@pytest.mark.parametrize("n,prec", [(5, 64), (8, 64), (8, 32), (6, 32), (7, 32), (4, 64), (4, 32), (6, 64),
+                                    (5, 32), (9, 32), (10, 32), (11, 32), (12, 32), (9, 64), (10, 64), (12, 64)])
 def test_grad_vs_oracle(gpu_lib, n, prec):
     N = 1024 + 17
     u, x, hel, order = setup(n, N, 40 + n)
@@ -52,9 +53,9 @@ def test_grad_vs_oracle(gpu_lib, n, prec):
         assert np.median(xerr) < 1e-12 and np.quantile(xerr, 0.99) < 1e-8 and xerr.max() < 1e-6
         assert np.median(lerr) < 1e-12 and np.quantile(lerr, 0.99) < 1e-9 and lerr.max() < 1e-6
     else:
-        # FP32: the stated median bound, and the 1% tail of events near a zero of the
-        # amplitude, where FP32 loses most digits
-        assert q[0] < 1e-4 and q[1] < 1e-2 and q[2] < 0.5
+        # FP32: the stated median bound; the 1% tail holds events near a zero of the
+        # amplitude, where FP32 loses most digits (measured p99 3.6e-4 .. 2.5e-3 for n = 5..12)
+        assert q[0] < 1e-4 and q[1] < 1e-3 and q[2] < 1e-2
         assert np.median(xerr) < 1e-5 and np.quantile(xerr, 0.99) < 1e-2
         assert np.median(lerr) < 1e-5 and np.quantile(lerr, 0.99) < 1e-2
 
@@ -100,11 +101,11 @@ def test_grad_closed_form_and_sum_rules(gpu_lib):
     assert np.median(np.abs((q0 * rho[:, :, 2] * g[:, :, 2]).sum(1)) / scale) < 1e-10
 
 
-@pytest.mark.parametrize("n,prec,N", [(6, 64, 256), (8, 32, 1024)])
+@pytest.mark.parametrize("n,prec,N", [(6, 64, 256), (8, 32, 1024), (12, 64, 128), (12, 32, 256)])
 def test_grad_vs_finite_differences_of_gpu_forward(gpu_lib, n, prec, N):
     """Central differences (h = 1e-6) of log w from bg_generate's FP64 forward, against the
-    FP64 adjoint (n = 6) and against the FP32 adjoint of the timed workload (n = 8, 1024
-    events)."""
+    FP64 adjoint (n = 6, 12), the FP32 adjoint of the timed workload (n = 8, 1024 events)
+    and the FP32 adjoint at n = 12."""
     u, x, hel, order = setup(n, N, 9)
     c = gpu_lib.config(n, prec=64)
     U, X, H, O = dev(u, x, hel, order)
@@ -140,12 +141,17 @@ def test_grad_vs_finite_differences_of_gpu_forward(gpu_lib, n, prec, N):
         assert np.median(xerr) < 1e-5
 
 
-@pytest.mark.parametrize("n,prec", [(9, 32), (12, 64)])
+@pytest.mark.parametrize("n,prec", [(3, 32), (13, 64)])
 def test_grad_unsupported_multiplicity(gpu_lib, n, prec):
     N = 4
-    u, x, hel, order = setup(n, N, 3)
+    U = torch.zeros((N, 4 * max(n - 2, 1)), dtype=torch.float64, device="cuda")
+    X = torch.full((N, 2), 0.5, dtype=torch.float64, device="cuda")
+    H = torch.zeros(N, dtype=torch.int32, device="cuda")
+    O = torch.zeros((N, n), dtype=torch.uint8, device="cuda")
+    c = gpu_lib.config(8, prec=prec)
+    c.n = n
     with pytest.raises(gpu_lib.BgError) as e:
-        gpu_lib.amp2_grad(gpu_lib.config(n, prec=prec), *dev(u, x, hel, order))
+        gpu_lib.amp2_grad(c, U, X, H, O)
     assert e.value.status == gpu_lib.BG_ENOTSUP
 
 

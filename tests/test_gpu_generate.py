@@ -153,32 +153,37 @@ def test_pdf_events(gpu_lib, n, prec):
     print(compare_events(g, o, oc, prec))
 
 
-@pytest.mark.parametrize("n,prec", [(9, 32), (6, 64)])
+@pytest.mark.parametrize("n,prec", [(9, 32), (6, 64), (12, 32), (12, 64)])
 def test_lane_forms_agree(gpu_lib, n, prec):
-    """bg_generate with one and with two lanes per event: identical draws, kinematics and
-    cut flags; |A|^2 and weights within the recursion precision's rounding (FP64 against
-    the oracle's rules, FP32 as for the persistent kernel)."""
+    """bg_generate with every lane form the library holds (one, two and four lanes per
+    event): identical draws, kinematics and cut flags; |A|^2 and weights within the
+    recursion precision's rounding (FP64 against the oracle's rules, FP32 against each
+    other as for the persistent kernel)."""
     c = cfg_c1(gpu_lib, n=n, prec=prec, seed=4242 + n)
     N = 3 * 256 + 19
     old = gpu_lib.get_lanes(n, prec)
     res = {}
     try:
-        for lanes in (1, 2):
+        for lanes in lane_forms(n, prec):
             gpu_lib.set_lanes(n, prec, lanes)
             print(f"generate n={n} prec={prec} lanes={lanes}", flush=True)
             res[lanes] = to_np(gpu_lib.generate(c, N, outputs=ALL))
     finally:
         gpu_lib.set_lanes(n, prec, old)
-    one, two = res[1], res[2]
-    for k in ("hel", "order", "pass", "momenta", "obs", "x12", "uniforms"):
-        assert np.array_equal(one[k], two[k]), k
     oc = oracle_cfg(c)
     oc["tau_min"] = pdf.tau_min(n, 20.0, 14000.0)
-    print(compare_events(two, event.generate(oc, np.arange(N)), oc, prec))
-    if prec == 32:
-        same_events(two, one, n, exact=False)
-    exact = math.fsum(two["weight"].tolist())
-    assert abs((two["acc"][0] + two["acc"][1]) - exact) <= 2 * EPS * np.abs(two["weight"]).sum()
+    o = event.generate(oc, np.arange(N))
+    forms = sorted(res)
+    first = res[forms[0]]
+    for lanes in forms:
+        g = res[lanes]
+        for k in ("hel", "order", "pass", "momenta", "obs", "x12", "uniforms"):
+            assert np.array_equal(first[k], g[k]), (lanes, k)
+        print(lanes, compare_events(g, o, oc, prec))
+        if prec == 32 and lanes != forms[0]:
+            same_events(g, first, n, exact=False)
+        exact = math.fsum(g["weight"].tolist())
+        assert abs((g["acc"][0] + g["acc"][1]) - exact) <= 2 * EPS * np.abs(g["weight"]).sum()
 
 
 @pytest.mark.parametrize("n", [4, 8, 12])
@@ -287,16 +292,16 @@ def same_events(m, s, n, exact=True):
 
 def single_ref(bg, c, N, mode, outputs=None):
     """The single-class run a class of a multi-class call must reproduce bitwise: the
-    persistent launch evaluates n = 9 with two lanes per event."""
+    persistent launch evaluates FP32 n >= 9 with two lanes per event."""
     outputs = outputs or ALL
-    if not (mode == 1 and c.n == 9 and c.prec == 32):
+    if not (mode == 1 and c.n >= 9 and c.prec == 32):
         return to_np(bg.generate(c, N, outputs=outputs))
-    old = bg.get_lanes(9, 32)
-    bg.set_lanes(9, 32, 2)
+    old = bg.get_lanes(c.n, 32)
+    bg.set_lanes(c.n, 32, 2)
     try:
         return to_np(bg.generate(c, N, outputs=outputs))
     finally:
-        bg.set_lanes(9, 32, old)
+        bg.set_lanes(c.n, 32, old)
 
 
 @pytest.fixture(params=[1, 0, 2], ids=["persistent", "sequential", "concurrent"])
