@@ -23,6 +23,19 @@ __device__ __forceinline__ T gsign(int mu) {
   return mu == 0 ? T(1) : T(-1);
 }
 
+// r + i i = x . k for a contravariant real four-vector k (the reverse sweep keeps its span
+// momenta contravariant)
+template <typename T>
+__device__ __forceinline__ void rdot_contra(const cv4<T>& x, const T k[4], T& r, T& i) {
+  r = x.re[0] * k[0];
+  i = x.im[0] * k[0];
+#pragma unroll
+  for (int mu = 1; mu < 4; ++mu) {
+    r = fmac(-x.re[mu], k[mu], r);
+    i = fmac(-x.im[mu], k[mu], i);
+  }
+}
+
 // from d = x.y (bilinear Minkowski): xb_mu += g_mu conj(y_mu) db
 template <typename T>
 __device__ __forceinline__ void cdot_adj(const cv4<T>& y, T dbr, T dbi, cv4<T>& xb) {
@@ -129,8 +142,8 @@ __device__ __forceinline__ void span_vertex_adj(const double (&k)[L][4], const c
     }
     T dr, di, ar, ai, br, bi;
     cdot(J[PA], J[PB], dr, di);
-    rdot(J[PA], kbv, ar, ai);
-    rdot(J[PB], ka, br, bi);
+    rdot_contra(J[PA], kbv, ar, ai);
+    rdot_contra(J[PB], ka, br, bi);
     // X += ca J[PB] - cb J[PA]
     T cabr = T(0), cabi = T(0), cbbr = T(0), cbbi = T(0);
     caxpy_adj_c(J[PB], Xb, cabr, cabi);
@@ -488,6 +501,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   cv4<T> V;
   SpanKLegs<L, T> ks{k};
   bg_forward<L, T>(ks, src, J, Sr, Si, V);
+  // bg_forward leaves the span scalars negated; the reverse sweep takes S itself
+  static_for<L, SP::count>([&](auto sc) {
+    Sr[decltype(sc)::value] = -Sr[decltype(sc)::value];
+    Si[decltype(sc)::value] = -Si[decltype(sc)::value];
+  });
   T mr, mi;
   cdot(e0, V, mr, mi);
   const double m2 = double(mr) * double(mr) + double(mi) * double(mi);

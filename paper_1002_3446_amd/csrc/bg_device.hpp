@@ -464,8 +464,10 @@ struct Spans {
   }
 };
 
-// Span momenta for the brackets, K[A..B] cast to T, and the propagators 1/K^2, from the FP64
-// leg momenta at every use (any precision, any workgroup size).
+// Span momenta for the brackets, K[A..B] cast to T and covariant (K_mu = g_mu K^mu, so that
+// J.K is a plain sum of products: the spatial signs are folded into K once instead of into
+// every product), and the propagators 1/K^2, from the FP64 leg momenta at every use (any
+// precision, any workgroup size).
 template <int L, typename T>
 struct SpanKLegs {
   const double (&k)[L][4];
@@ -473,8 +475,9 @@ struct SpanKLegs {
   __device__ __forceinline__ void K(T out[4]) const {
     double d[4];
     span_sum<A, B, L>(k, d);
+    out[0] = T(d[0]);
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) out[mu] = T(d[mu]);
+    for (int mu = 1; mu < 4; ++mu) out[mu] = T(-d[mu]);
   }
   template <int A, int B>
   __device__ __forceinline__ T prop() const {
@@ -485,7 +488,8 @@ struct SpanKLegs {
 };
 
 // The same values from a per-lane table in LDS, filled once per event: every span momentum
-// summed left to right in FP64 then cast to float, every propagator 1/K^2 formed in FP64.
+// summed left to right in FP64 then cast to float (covariant), every propagator 1/K^2 formed
+// in FP64.
 // Layout [span][lane] with LANES lanes per workgroup, so a wave's accesses are contiguous.
 template <int L, int LANES>
 struct SpanKLds {
@@ -496,12 +500,12 @@ struct SpanKLds {
     static_for<0, L>([&](auto ac) {
       constexpr int a = decltype(ac)::value;
       double acc[4] = {k[a][0], k[a][1], k[a][2], k[a][3]};
-      kt[SP::at(a, a) * LANES] = make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
+      kt[SP::at(a, a) * LANES] = make_float4(float(acc[0]), float(-acc[1]), float(-acc[2]), float(-acc[3]));
       static_for<a + 1, L>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) acc[mu] += k[b][mu];
-        kt[SP::at(a, b) * LANES] = make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
+        kt[SP::at(a, b) * LANES] = make_float4(float(acc[0]), float(-acc[1]), float(-acc[2]), float(-acc[3]));
         // K^2 in FP64, its reciprocal in FP32 (within 1 ulp of the rounded K^2's)
         if (b - a + 1 < L) pt[SP::at(a, b) * LANES] = __builtin_amdgcn_rcpf(float(minkowski_sq(acc)));
       });
@@ -541,15 +545,59 @@ __device__ __forceinline__ void cdot(const cv4<T>& x, const cv4<T>& y, T& r, T& 
   }
 }
 
-// r + i i = x . k for a real four-vector k
+// r + i i = x . k for a real four-vector k given covariant (k_mu = g_mu k^mu)
 template <typename T>
 __device__ __forceinline__ void rdot(const cv4<T>& x, const T k[4], T& r, T& i) {
   r = x.re[0] * k[0];
   i = x.im[0] * k[0];
 #pragma unroll
   for (int mu = 1; mu < 4; ++mu) {
-    r = fmac(-x.re[mu], k[mu], r);
-    i = fmac(-x.im[mu], k[mu], i);
+    r = fmac(x.re[mu], k[mu], r);
+    i = fmac(x.im[mu], k[mu], i);
+  }
+}
+
+// K_A - K_B contravariant, from covariant K_A, K_B (exact: only signs differ)
+template <typename T>
+__device__ __forceinline__ T kdiff(const T (&ka)[4], const T (&kb)[4], int mu) {
+  return mu == 0 ? ka[0] - kb[0] : kb[mu] - ka[mu];
+}
+
+// The same dot with its imaginary part returned negated (ni = -i, exactly: every step is the
+// negation of cdot's), for products whose consumer then needs no negated operand.
+template <typename T>
+__device__ __forceinline__ void cdot_ni(const cv4<T>& x, const cv4<T>& y, T& r, T& ni) {
+  r = fmac(-x.im[0], y.im[0], x.re[0] * y.re[0]);
+  ni = fmac(-x.im[0], y.re[0], -x.re[0] * y.im[0]);
+#pragma unroll
+  for (int mu = 1; mu < 4; ++mu) {
+    r = fmac(-x.re[mu], y.re[mu], r);
+    r = fmac(x.im[mu], y.im[mu], r);
+    ni = fmac(x.re[mu], y.im[mu], ni);
+    ni = fmac(x.im[mu], y.re[mu], ni);
+  }
+}
+
+// x . k with k covariant, its real part returned negated (nr = -r, exactly)
+template <typename T>
+__device__ __forceinline__ void rdot_nr(const cv4<T>& x, const T k[4], T& nr, T& i) {
+  nr = -x.re[0] * k[0];
+  i = x.im[0] * k[0];
+#pragma unroll
+  for (int mu = 1; mu < 4; ++mu) {
+    nr = fmac(-x.re[mu], k[mu], nr);
+    i = fmac(x.im[mu], k[mu], i);
+  }
+}
+
+// acc += (cr - i nci) * y, the conjugate-sign form of caxpy (same roundings as
+// caxpy(cr, -nci, y, acc))
+template <typename T>
+__device__ __forceinline__ void caxpy_nci(T cr, T nci, const cv4<T>& y, cv4<T>& acc) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    acc.re[mu] = fmac(nci, y.im[mu], fmac(cr, y.re[mu], acc.re[mu]));
+    acc.im[mu] = fmac(-nci, y.re[mu], fmac(cr, y.im[mu], acc.im[mu]));
   }
 }
 
@@ -564,6 +612,8 @@ __device__ __forceinline__ void caxpy(T cr, T ci, const cv4<T>& y, cv4<T>& acc) 
 }
 
 // One span [A..B] of the recursion: its bracket sum V (Eqs. 3.1-3.2, regrouped as above).
+// The span scalars are carried negated (nS = -S, exactly), which turns the S terms'
+// subtractions into plain multiply-adds; sr, si return -S of [A..B].
 template <int L, int A, int B, typename T, typename KS>
 __device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Spans<L>::count],
                                             const T (&Sr)[Spans<L>::count], const T (&Si)[Spans<L>::count],
@@ -584,41 +634,41 @@ __device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Span
     T ka[4], kb[4];
     ks.template K<A, i>(ka);
     ks.template K<i + 1, B>(kb);
-    T dr, di, ar, ai, br, bi;
+    T dr, di, ar, ai, nbr, bi;
     cdot(J[PA], J[PB], dr, di);
     rdot(J[PA], kb, ar, ai);
-    rdot(J[PB], ka, br, bi);
+    rdot_nr(J[PB], ka, nbr, bi);
     caxpy(ar, ai, J[PB], X);
-    caxpy(-br, -bi, J[PA], X);
+    caxpy_nci(nbr, bi, J[PA], X);  // X -= (J[PB].K_A) J[PA]
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-      const T dk = ka[mu] - kb[mu];
+      const T dk = kdiff(ka, kb, mu);
       Y.re[mu] = fmac(dr, dk, Y.re[mu]);
       Y.im[mu] = fmac(di, dk, Y.im[mu]);
     }
-    sr += dr;
-    si += di;
+    sr -= dr;
+    si -= di;
   });
   // four-gluon brackets: 2 (JA.JC) JB over pairs of splits
   static_for<A, B - 1>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     static_for<i + 1, B>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      T dr, di;
-      cdot(J[SP::at(A, i)], J[SP::at(j + 1, B)], dr, di);
-      caxpy(dr, di, J[SP::at(i + 1, j)], X);
+      T dr, ndi;
+      cdot_ni(J[SP::at(A, i)], J[SP::at(j + 1, B)], dr, ndi);
+      caxpy_nci(dr, ndi, J[SP::at(i + 1, j)], X);
     });
   });
   // -(JA.JB) JC and -(JC.JB) JA through the span scalars S
   static_for<A + 1, B>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     constexpr int Sx = SP::at(A, j);
-    caxpy(-Sr[Sx], -Si[Sx], J[SP::at(j + 1, B)], Y);
+    caxpy(Sr[Sx], Si[Sx], J[SP::at(j + 1, B)], Y);
   });
   static_for<A, B - 1>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     constexpr int Sx = SP::at(i + 1, B);
-    caxpy(-Sr[Sx], -Si[Sx], J[SP::at(A, i)], Y);
+    caxpy(Sr[Sx], Si[Sx], J[SP::at(A, i)], Y);
   });
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
@@ -627,8 +677,8 @@ __device__ __forceinline__ void span_vertex(const KS& ks, const cv4<T> (&J)[Span
   }
 }
 
-// Forward recursion: fills every stored current J and span scalar S, and returns the
-// undivided bracket sum V of the full span [0..L-1].
+// Forward recursion: fills every stored current J and negated span scalar -S, and returns
+// the undivided bracket sum V of the full span [0..L-1].
 template <int L, typename T, typename KS>
 __device__ __forceinline__ void bg_forward(const KS& ks, const cv4<T> (&src)[L],
                                            cv4<T> (&J)[Spans<L>::count], T (&Sr)[Spans<L>::count],
@@ -725,16 +775,20 @@ __device__ __forceinline__ rv4<T> real_polarisation(const double p[4], T c, T s)
 
 // x . y (metric (+,-,-,-)) of real four-vectors
 template <typename T>
-__device__ __forceinline__ T vdot(const rv4<T>& x, const T (&y)[4]) {
-  T r = x.v[0] * y[0];
-  r = fmac(-x.v[1], y[1], r);
-  r = fmac(-x.v[2], y[2], r);
-  return fmac(-x.v[3], y[3], r);
+__device__ __forceinline__ T vdot(const rv4<T>& x, const rv4<T>& y) {
+  T r = x.v[0] * y.v[0];
+  r = fmac(-x.v[1], y.v[1], r);
+  r = fmac(-x.v[2], y.v[2], r);
+  return fmac(-x.v[3], y.v[3], r);
 }
 
+// x . k for k given covariant
 template <typename T>
-__device__ __forceinline__ T vdot(const rv4<T>& x, const rv4<T>& y) {
-  return vdot(x, y.v);
+__device__ __forceinline__ T vdot_cov(const rv4<T>& x, const T (&k)[4]) {
+  T r = x.v[0] * k[0];
+  r = fmac(x.v[1], k[1], r);
+  r = fmac(x.v[2], k[2], r);
+  return fmac(x.v[3], k[3], r);
 }
 
 // acc += c y
@@ -744,7 +798,8 @@ __device__ __forceinline__ void vaxpy(T c, const rv4<T>& y, rv4<T>& acc) {
   for (int mu = 0; mu < 4; ++mu) acc.v[mu] = fmac(c, y.v[mu], acc.v[mu]);
 }
 
-// One span [A..B] with real currents: its bracket sum V (regrouped as span_vertex).
+// One span [A..B] with real currents: its bracket sum V (regrouped as span_vertex; span
+// scalars negated as there).
 template <int L, int A, int B, typename T, typename KS>
 __device__ __forceinline__ void span_vertex_r(const KS& ks, const rv4<T> (&J)[Spans<L>::count],
                                               const T (&S)[Spans<L>::count], rv4<T>& V, T& sv) {
@@ -761,11 +816,11 @@ __device__ __forceinline__ void span_vertex_r(const KS& ks, const rv4<T> (&J)[Sp
     ks.template K<A, i>(ka);
     ks.template K<i + 1, B>(kb);
     const T d = vdot(J[PA], J[PB]);
-    vaxpy(vdot(J[PA], kb), J[PB], X);
-    vaxpy(-vdot(J[PB], ka), J[PA], X);
+    vaxpy(vdot_cov(J[PA], kb), J[PB], X);
+    vaxpy(-vdot_cov(J[PB], ka), J[PA], X);
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) Y.v[mu] = fmac(d, ka[mu] - kb[mu], Y.v[mu]);
-    sv += d;
+    for (int mu = 0; mu < 4; ++mu) Y.v[mu] = fmac(d, kdiff(ka, kb, mu), Y.v[mu]);
+    sv -= d;
   });
   static_for<A, B - 1>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
@@ -776,11 +831,11 @@ __device__ __forceinline__ void span_vertex_r(const KS& ks, const rv4<T> (&J)[Sp
   });
   static_for<A + 1, B>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
-    vaxpy(-S[SP::at(A, j)], J[SP::at(j + 1, B)], Y);
+    vaxpy(S[SP::at(A, j)], J[SP::at(j + 1, B)], Y);
   });
   static_for<A, B - 1>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    vaxpy(-S[SP::at(i + 1, B)], J[SP::at(A, i)], Y);
+    vaxpy(S[SP::at(i + 1, B)], J[SP::at(A, i)], Y);
   });
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) V.v[mu] = fmac(T(2), X.v[mu], Y.v[mu]);
