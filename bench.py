@@ -387,6 +387,8 @@ def main():
                     help="with --no-extras: still time the recursion kernel (bg_amp2) alone")
     ap.add_argument("--adjoint", action="store_true",
                     help="with --no-extras: still time the forward + adjoint through the torch Function")
+    ap.add_argument("--adjoint-n", type=int, default=8, help="multiplicity of the --adjoint timing")
+    ap.add_argument("--adjoint-prec", type=int, default=32, choices=(32, 64), help="precision of the --adjoint timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scales HBM counters)")
     a = ap.parse_args()
@@ -476,7 +478,8 @@ def main():
     if a.recursion and a.no_extras:
         line["recursion_kernel"] = recursion_rate(bg, torch)
     if a.adjoint and a.no_extras:
-        line["adjoint"] = adjoint_rate(bg, torch, steps=2)
+        line["adjoint"] = adjoint_rate(bg, torch, N=1 << (20 if a.adjoint_n <= 8 else 18), steps=2,
+                                       n=a.adjoint_n, prec=a.adjoint_prec)
     if not a.no_extras:
         extras = {}
         cfg64 = bg.config(n, prec=64, sqrt_s=14000.0, use_pdf=1, random_order=1, seed=0xB6000001)
