@@ -45,28 +45,64 @@ __global__ __launch_bounds__(kKinBlock) void k_kin_multi(const MultiClass* __res
   }
 }
 
-// The per-class tile bodies are separate functions (not inlined into the kernel): each is
+// The next tile of the queue for the whole (one-wave) workgroup.
+__device__ __forceinline__ int next_tile(int* counter, int* s_tile) {
+  if (threadIdx.x == 0) *s_tile = atomicAdd(counter, 1);
+  __syncthreads();
+  const int t = __builtin_amdgcn_readfirstlane(*s_tile);
+  __syncthreads();
+  return t;
+}
+
+// The per-multiplicity bodies are separate functions (not inlined into the kernel): each is
 // register-allocated on its own, which keeps the kernel's compile time near the sum of the
-// single-class kernels' instead of growing with the square of the whole body.
+// single-class kernels' instead of growing with the square of the whole body.  A call saves
+// and restores the registers the calling convention assigns to the callee, so each function
+// runs a whole run of tiles of its multiplicity (the queue is ordered by n, so a wave calls
+// each at most once) and returns the first tile of another multiplicity, or one past the end.
 template <int N>
-__device__ __attribute__((noinline)) void staged_tile(const MultiClass& mc, const Tile& tl, const double* __restrict__ stage,
-                                            void* lds, CSum& w, CSum& w2) {
-  const double* buf = stage + mc.stage_off;  // slot = the class's local event index
-  for (int64_t i = tl.first + threadIdx.x; i < tl.first + tl.count; i += kMultiBlock) {
-    const double x = rec_one<N>(mc.C, i, i, buf, reinterpret_cast<LdsTable<N>*>(lds));
-    w = cs_add(w, CSum{x, 0.0});
-    w2 = cs_add(w2, CSum{x * x, 0.0});
+__device__ __attribute__((noinline)) int staged_run(const MultiClass* __restrict__ classes,
+                                                    const Tile* __restrict__ tiles, int ntiles, int* counter,
+                                                    int* s_tile, int t, const double* __restrict__ stage, void* lds,
+                                                    double* partials) {
+  while (t < ntiles) {
+    const Tile tl = tiles[t];
+    const MultiClass& mc = classes[tl.cls];
+    if (mc.n != N) return t;
+    const double* buf = stage + mc.stage_off;  // slot = the class's local event index
+    CSum w{0.0, 0.0}, w2{0.0, 0.0};
+    for (int64_t i = tl.first + threadIdx.x; i < tl.first + tl.count; i += kMultiBlock) {
+      const double x = rec_one<N>(mc.C, i, i, buf, reinterpret_cast<LdsTable<N>*>(lds));
+      w = cs_add(w, CSum{x, 0.0});
+      w2 = cs_add(w2, CSum{x * x, 0.0});
+    }
+    block_reduce_store(w, w2, partials + 4 * (int64_t)t);
+    __syncthreads();
+    t = next_tile(counter, s_tile);
   }
+  return t;
 }
 
 template <int N>
-__device__ __attribute__((noinline)) void paired_tile(const MultiClass& mc, const Tile& tl, CSum& w, CSum& w2) {
+__device__ __attribute__((noinline)) int paired_run(const MultiClass* __restrict__ classes,
+                                                    const Tile* __restrict__ tiles, int ntiles, int* counter,
+                                                    int* s_tile, int t, double* partials) {
   const int g = (int)(threadIdx.x & 1u);
-  for (int64_t i = tl.first + (threadIdx.x >> 1); i < tl.first + tl.count; i += kMultiBlock / 2) {
-    const double x = generate_one<N, float, 2>(mc.C, i, PermLds{nullptr, 0}, g);
-    w = cs_add(w, CSum{x, 0.0});
-    w2 = cs_add(w2, CSum{x * x, 0.0});
+  while (t < ntiles) {
+    const Tile tl = tiles[t];
+    const MultiClass& mc = classes[tl.cls];
+    if (mc.n != N) return t;
+    CSum w{0.0, 0.0}, w2{0.0, 0.0};
+    for (int64_t i = tl.first + (threadIdx.x >> 1); i < tl.first + tl.count; i += kMultiBlock / 2) {
+      const double x = generate_one<N, float, 2>(mc.C, i, PermLds{nullptr, 0}, g);
+      w = cs_add(w, CSum{x, 0.0});
+      w2 = cs_add(w2, CSum{x * x, 0.0});
+    }
+    block_reduce_store(w, w2, partials + 4 * (int64_t)t);
+    __syncthreads();
+    t = next_tile(counter, s_tile);
   }
+  return t;
 }
 
 __global__ __launch_bounds__(kMultiBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate_multi(
@@ -74,28 +110,19 @@ __global__ __launch_bounds__(kMultiBlock) __attribute__((amdgpu_waves_per_eu(1, 
     const double* __restrict__ stage, double* partials) {
   __shared__ LdsTable<8> lds;  // the span table of the staged classes (n <= 8 fits n = 8's)
   __shared__ int s_tile;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(s_tile);
-    __syncthreads();
-    if (t >= ntiles) break;
-    const Tile tl = tiles[t];
-    const MultiClass& mc = classes[tl.cls];
-    CSum w{0.0, 0.0}, w2{0.0, 0.0};
-    switch (mc.n) {
-      case 4: staged_tile<4>(mc, tl, stage, &lds, w, w2); break;
-      case 5: staged_tile<5>(mc, tl, stage, &lds, w, w2); break;
-      case 6: staged_tile<6>(mc, tl, stage, &lds, w, w2); break;
-      case 7: staged_tile<7>(mc, tl, stage, &lds, w, w2); break;
-      case 8: staged_tile<8>(mc, tl, stage, &lds, w, w2); break;
-      case 9: paired_tile<9>(mc, tl, w, w2); break;
-      case 10: paired_tile<10>(mc, tl, w, w2); break;
-      case 11: paired_tile<11>(mc, tl, w, w2); break;
-      default: paired_tile<12>(mc, tl, w, w2); break;
+  int t = next_tile(counter, &s_tile);
+  while (t < ntiles) {
+    switch (classes[tiles[t].cls].n) {
+      case 4: t = staged_run<4>(classes, tiles, ntiles, counter, &s_tile, t, stage, &lds, partials); break;
+      case 5: t = staged_run<5>(classes, tiles, ntiles, counter, &s_tile, t, stage, &lds, partials); break;
+      case 6: t = staged_run<6>(classes, tiles, ntiles, counter, &s_tile, t, stage, &lds, partials); break;
+      case 7: t = staged_run<7>(classes, tiles, ntiles, counter, &s_tile, t, stage, &lds, partials); break;
+      case 8: t = staged_run<8>(classes, tiles, ntiles, counter, &s_tile, t, stage, &lds, partials); break;
+      case 9: t = paired_run<9>(classes, tiles, ntiles, counter, &s_tile, t, partials); break;
+      case 10: t = paired_run<10>(classes, tiles, ntiles, counter, &s_tile, t, partials); break;
+      case 11: t = paired_run<11>(classes, tiles, ntiles, counter, &s_tile, t, partials); break;
+      default: t = paired_run<12>(classes, tiles, ntiles, counter, &s_tile, t, partials); break;
     }
-    block_reduce_store(w, w2, partials + 4 * (int64_t)t);
-    __syncthreads();
   }
 }
 
