@@ -250,6 +250,7 @@ def cpu_model() -> str:
 
 
 BENCH_SEED = {8: 0xB6000001, 12: 0xB6000002}
+BENCH_SEED.update({n: 0xB6000003 + n for n in (4, 5, 6, 7, 9, 10, 11)})  # the mixed workload's
 CHUNK = 4096
 
 
@@ -298,7 +299,8 @@ def cpu_legs(seconds: float = 10.0, accuracy_events: int = 1 << 16):
     """Runs before the GPU is touched (the worker processes are forked).  Returns the CPU
     baseline (the oracle on all host cores and on one, a bounded sample of the n = 8
     workload) and the oracle's |A|^2 of the first accuracy_events events of the n = 8 and
-    n = 12 workloads (the reference of the accuracy block)."""
+    n = 12 workloads and of 2^13 events of every other n = 4..11 (the reference of the
+    accuracy block)."""
     import multiprocessing as mp
 
     import numpy as np
@@ -309,8 +311,9 @@ def cpu_legs(seconds: float = 10.0, accuracy_events: int = 1 << 16):
         single = _oracle_timed((0, 1, seconds / 4))
         res = pool.map(_oracle_timed, [(w, cores, seconds) for w in range(cores)])
         ref = {}
-        for n in (8, 12):
-            parts = pool.map(_oracle_amp2, [(n, lo, lo + CHUNK) for lo in range(0, accuracy_events, CHUNK)])
+        for n in range(4, 13):
+            ne = accuracy_events if n in (8, 12) else accuracy_events // 8
+            parts = pool.map(_oracle_amp2, [(n, lo, lo + CHUNK) for lo in range(0, ne, CHUNK)])
             ref[n] = tuple(np.concatenate([p[i] for p in parts]) for i in range(3))
     events = sum(r[0] for r in res)
     wall = max(r[1] for r in res)
@@ -323,7 +326,7 @@ def cpu_legs(seconds: float = 10.0, accuracy_events: int = 1 << 16):
 
 def accuracy_block(bg, torch, ref):
     """Per-event relative error of |A|^2 against the oracle (float64) on the first events of
-    the n = 8 and n = 12 workloads, FP32 and FP64 recursion, over the helicity
+    the workloads (2^16 at n = 8 and 12, 2^13 at the other n), FP32 and FP64 recursion, over the helicity
     configurations whose amplitude does not vanish identically; the maximum also relative
     to the event's size max(|A|^2, Parke-Taylor |A|^2 of its ordering), which bounds the
     FP32 tail of events near a zero of the amplitude."""
@@ -470,6 +473,12 @@ def main():
         "paper_context": {"tesla_fp32_n8_events_per_s": PAPER_N8_EVENTS_PER_S,
                           "note": "paper Table 1, NVIDIA Tesla, real polarisations, LHAPDF; not the same workload"},
     }
+    # the ceilings as this GPU sustains them: plain multiply-add chains (scalar FP32, FP64)
+    fma32, fma64 = bg.fma_rate(32), bg.fma_rate(64)
+    exe = fe * N / (launch_ms * 1e-3) / 1e12
+    line["calibration"] = {"fma_fp32_tflops": fma32, "fma_fp64_tflops": fma64,
+                           "executed_frac_of_measured_fma": exe / (fma32 if a.prec == 32 else fma64),
+                           "note": "bg_fma_rate: chains of independent FMAs, all CUs, 8 waves/SIMD; scalar FP32"}
     if n == 8:
         line["sigma"] = sigma_block(bg, torch, N)
     if ref is not None:

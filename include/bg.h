@@ -133,7 +133,9 @@ typedef struct {
  * Device workspace (partials, staging) is allocated stream-ordered from a library-owned
  * memory pool per device, which keeps up to 4 GiB reserved between calls.
  * cfgs, counts, outs: host arrays of ncfg entries; ins: NULL or ncfg entries.
- * counts[k] = 0 is allowed.  Errors: BG_EINVAL (ncfg < 1 or > 16, counts < 0,
+ * counts[k] = 0 is allowed.  Given draws are not validated; an event whose uniforms or
+ * x1, x2 are not finite gets pass = 0 and w = 0, so it never enters the totals, and its
+ * momenta, observables, |A|^2 and log w are not finite.  Errors: BG_EINVAL (ncfg < 1 or > 16, counts < 0,
  * bad parameters), BG_ENOTSUP (n, prec, or a lane form not built), BG_ENOMEM. */
 int bg_generate(const bg_config *cfgs, int ncfg, const int64_t *counts,
                 const bg_inputs *ins, const bg_outputs *outs, void *stream);
@@ -154,7 +156,8 @@ int bg_generate_noalloc(const bg_config *cfg, int64_t count, const bg_inputs *in
 
 /* |A(sigma; h)|^2 for given physical momenta (Sec. 3, Eqs. 3.1, 3.2, 3.6).
  * mom [N][n][4] FP64, hel [N], order [N][n]; amp2_out [N] FP64.  Span invariants K^2
- * are formed in FP64 for both precisions.  N = 0 is a no-op. */
+ * are formed in FP64 for both precisions.  N = 0 is a no-op.  Non-finite momenta give a
+ * non-finite |A|^2 for that event only. */
 int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
             const uint8_t *order, double *amp2_out, void *stream);
 
@@ -170,7 +173,8 @@ int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
  * uniforms [N][4(n-2)], x12 [N][2] (ignored unless use_pdf), hel [N], order [N][n];
  * gout [N] (dL/dlog w, may be NULL = all ones); grad_u [N][4(n-2)], grad_x [N][2]
  * (zeros when use_pdf = 0) receive gout * d log w_int; logw [N] optional.
- * Events with |A|^2 = 0 get log w = -inf and zero gradients.
+ * Events with |A|^2 = 0 or not finite (non-finite inputs) get log w = -inf and zero
+ * gradients.
  * Supported for n = 4..12 in both precisions.  The recursion's reverse sweep runs one lane
  * per event for FP32 n <= 5 and FP64 n = 4, else four lanes per event (each holding one
  * Lorentz component of every current and of its adjoint).  BG_ENOTSUP for real
@@ -266,6 +270,14 @@ int bg_get_form(int n, int prec, int *form);
  * totals agree within the compensated-sum bound.  Errors: BG_EINVAL for another value. */
 int bg_set_mixed_launch(int mode);
 int bg_get_mixed_launch(void);
+
+/* Calibration of the roofline: the fused multiply-add rate (TFLOP/s, a multiply-add counted
+ * as two) that this GPU's vector ALUs sustain in precision prec (32 or 64), measured with
+ * chains of independent multiply-adds and nothing else, all compute units at eight waves per
+ * SIMD (about 10 ms; synchronises the stream).  The published MI355X vector peaks count
+ * packed FP32 (157.3 TFLOP/s); this library emits scalar FP32, whose ceiling is half that.
+ * Errors: BG_EINVAL (prec, NULL), BG_EHIP. */
+int bg_fma_rate(int prec, double *tflops, void *stream);
 
 /* Static message for a status code. */
 const char *bg_strerror(int status);

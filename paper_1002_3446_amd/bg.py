@@ -87,9 +87,10 @@ _lib.bg_set_mixed_launch.argtypes = [ctypes.c_int]
 _lib.bg_get_mixed_launch.argtypes = []
 _lib.bg_strerror.restype = ctypes.c_char_p
 _lib.bg_strerror.argtypes = [ctypes.c_int]
+_lib.bg_fma_rate.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
 for _f in ("bg_generate", "bg_generate_noalloc", "bg_hist_accumulate", "bg_hist_read", "bg_amp2", "bg_amp2_grad", "bg_set_launch", "bg_get_launch", "bg_version",
            "bg_set_mixed_launch", "bg_get_mixed_launch", "bg_set_lanes", "bg_get_lanes", "bg_set_form",
-           "bg_get_form"):
+           "bg_get_form", "bg_fma_rate"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -106,6 +107,13 @@ def _check(fn: str, status: int):
 
 def version() -> int:
     return _lib.bg_version()
+
+
+def fma_rate(prec: int) -> float:
+    """TFLOP/s of plain fused multiply-add chains in FP32 or FP64 on the current device."""
+    v = ctypes.c_double()
+    _check("bg_fma_rate", _lib.bg_fma_rate(prec, ctypes.byref(v), _stream(torch.device("cuda"))))
+    return v.value
 
 
 def source_hash() -> str:

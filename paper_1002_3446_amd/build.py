@@ -81,7 +81,8 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
     units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"),
               [f'-DBG_SOURCE_HASH="{source_hash()}"'], 0),
              (os.path.join(CSRC, "bg_finalize.hip"), os.path.join(OUT_DIR, "bg_finalize.o"), [], 0),
-             (os.path.join(CSRC, "bg_hist.hip"), os.path.join(OUT_DIR, "bg_hist.o"), [], 0)]
+             (os.path.join(CSRC, "bg_hist.hip"), os.path.join(OUT_DIR, "bg_hist.o"), [], 0),
+             (os.path.join(CSRC, "bg_probe.hip"), os.path.join(OUT_DIR, "bg_probe.o"), [], 0)]
     if set(range(4, 13)) <= set(ns) and 32 in precs:
         units.append((os.path.join(CSRC, "bg_multi.hip"), os.path.join(OUT_DIR, "bg_multi_p32.o"), [], 1000))
     for n in ns:

@@ -463,6 +463,7 @@ constexpr size_t kMultiStageMax = size_t(8) << 30;
 
 int generate_multi(const bg_config* cfgs, const GenClass* G, const bg_outputs* outs, const std::vector<int>& ks,
                    hipStream_t s) {
+  if (!launch_generate_multi_p32) return BG_ENOTSUP;
   std::vector<int> order;  // staged classes first (kinematics workgroup order), then the others
   for (int k : ks)
     if (split_form(cfgs[k].n, 32)) order.push_back(k);
@@ -638,6 +639,17 @@ int bg_generate_noalloc(const bg_config* cfg, int64_t count, const bg_inputs* in
   return st;
 }
 
+
+int bg_fma_rate(int prec, double* tflops, void* stream) {
+  if ((prec != 32 && prec != 64) || !tflops) return BG_EINVAL;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BG_EHIP;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) return BG_EHIP;
+  double r = 0.0;
+  const int st = from_hip(measure_fma_rate(prec, 4096, ncu, &r, (hipStream_t)stream));
+  if (st == BG_OK) *tflops = r * 1e-12;
+  return st;
+}
 
 int bg_version(void) { return 10100; }
 

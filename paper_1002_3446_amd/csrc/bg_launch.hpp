@@ -124,9 +124,16 @@ struct Tile {
 constexpr int kKinBlock = 128;   // workgroup of the kinematics kernels
 constexpr int kMultiBlock = 64;  // workgroup (one wave) of the persistent kernel
 
-hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, int nstaged, int64_t kin_blocks,
-                                     const Tile* tiles, int ntiles, int* counter, double* stage, double* partials,
-                                     int grid, hipStream_t s);
+// Sustained multiply-add rate of the VALU (bg_probe.hip): flops per second of `iters` rounds
+// of 16 independent fused multiply-add chains per lane, at eight waves per SIMD on ncu
+// compute units; synchronises the stream.
+hipError_t measure_fma_rate(int prec, int iters, int ncu, double* flops_per_s, hipStream_t s);
+
+// (weak: a library built without bg_multi.hip runs mixed calls one class after another)
+__attribute__((weak)) hipError_t launch_generate_multi_p32(const MultiClass* classes, int nclasses, int nstaged,
+                                                           int64_t kin_blocks, const Tile* tiles, int ntiles,
+                                                           int* counter, double* stage, double* partials, int grid,
+                                                           hipStream_t s);
 
 // Histogram axes of one bg_hist_accumulate / bg_hist_read call (bg_hist.hip): axis a
 // reads obs column `column`, bins [lo, hi) into nbins, and owns bins first_bin ..

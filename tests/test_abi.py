@@ -95,3 +95,22 @@ def test_host_error_paths():
         bg.set_lanes(n, 32, l)
     b, k = ctypes.c_int(), ctypes.c_int()
     assert lib.bg_get_launch(8, 32, ctypes.byref(b), ctypes.byref(k)) == bg.BG_OK and b.value in (64, 128, 192, 256)
+
+
+@need_lib
+def test_hip_error_path_without_device():
+    """Without a GPU the first HIP call of a valid request fails: the entry points return
+    BG_EHIP (nothing is enqueued, no pointer is dereferenced on the host)."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible")
+    from paper_1002_3446_amd import bg
+    lib = bg.raw()
+    c = bg.config(8, prec=32)
+    counts = (ctypes.c_int64 * 1)(1000)
+    outs = bg.BgOutputs()
+    outs.weight = ctypes.c_void_p(0x10000)
+    assert lib.bg_generate(ctypes.byref(c), 1, counts, None, ctypes.byref(outs), None) == bg.BG_EHIP
+    p = ctypes.c_void_p(0x10000)
+    assert lib.bg_amp2(8, 32, 4, p, p, p, p, None) == bg.BG_EHIP
+    assert lib.bg_generate_noalloc(ctypes.byref(c), 10, None, ctypes.byref(outs), None) == bg.BG_EHIP

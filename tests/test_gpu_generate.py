@@ -214,6 +214,45 @@ def test_sampler_extreme_uniforms(gpu_lib, n):
     assert np.all((g >= oc["tau_min"]) & (g < 1.0))
 
 
+@pytest.mark.parametrize("n,prec", [(8, 32), (12, 32), (6, 64)])
+def test_non_finite_inputs(gpu_lib, n, prec):
+    """Given draws that are not finite (NaN or +-inf in a RAMBO uniform, x1 or x2): those
+    events get pass = 0 and w = 0 and non-finite |A|^2, the others are bitwise those of a
+    call with clean inputs, and the totals stay finite (the boundary's convention)."""
+    N = 600
+    c = cfg_c1(gpu_lib, n=n, prec=prec)
+    u = inputs.rambo_uniforms(9, N, n)
+    x = inputs.x_fractions(9, N, pdf.tau_min(n, 20.0, 14000.0))
+    hel = inputs.helicity_words(9, N, n)
+    order = inputs.orderings(9, N, n)
+    bad = {3: ("u", np.nan), 10: ("u", np.inf), 17: ("u", -np.inf), 64: ("x1", np.nan), 65: ("x2", np.inf),
+           130: ("x1", -np.inf), 599: ("u", np.nan)}
+    ub, xb = u.copy(), x.copy()
+    for i, (where, v) in bad.items():
+        if where == "u":
+            ub[i, (i % (4 * (n - 2)))] = v
+        else:
+            xb[i, 0 if where == "x1" else 1] = v
+
+    def run(uu, xx):
+        ins = dict(uniforms=torch.tensor(uu, device="cuda"), x12=torch.tensor(xx, device="cuda"),
+                   hel=torch.tensor(hel.astype(np.int64), device="cuda").to(torch.int32),
+                   order=torch.tensor(order, device="cuda"))
+        return to_np(gpu_lib.generate(c, N, inputs=ins, outputs=("weight", "amp2", "pass", "obs", "logw", "acc")))
+
+    print(f"non-finite inputs n={n} prec={prec}", flush=True)
+    clean, dirty = run(u, x), run(ub, xb)
+    idx = np.array(sorted(bad))
+    good = np.setdiff1d(np.arange(N), idx)
+    assert np.all(dirty["pass"][idx] == 0) and np.all(dirty["weight"][idx] == 0.0)
+    assert not np.any(np.isfinite(dirty["amp2"][idx])) and not np.any(np.isfinite(dirty["logw"][idx]))
+    for k in ("weight", "amp2", "pass", "obs", "logw"):
+        assert np.array_equal(dirty[k][good], clean[k][good]), k
+    assert np.all(np.isfinite(dirty["acc"]))
+    exact = math.fsum(dirty["weight"].tolist())
+    assert abs((dirty["acc"][0] + dirty["acc"][1]) - exact) <= 2 * EPS * np.abs(dirty["weight"]).sum()
+
+
 def test_given_inputs(gpu_lib):
     """With caller-supplied uniforms, x1, x2, helicities and orderings the inverse-CDF
     conditioning drops out: |A|^2 meets the FP64 rules without any widening."""
