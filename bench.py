@@ -441,11 +441,13 @@ def main():
     # timed unit is then the whole bg_generate call (both kernels, every chunk)
     real_t = "float" if a.prec == 32 else "double"
     peak = PEAK_FP32 if a.prec == 32 else PEAK_FP64
+    lanes = bg.get_lanes(n, a.prec)
     if n <= 8 and a.prec == 32:
         kname = f"k_kin<{n}>+k_rec<{n}>"
+    elif lanes == 1:
+        kname = f"k_generate<{n},{real_t}>"
     else:
-        lanes = bg.get_lanes(n, a.prec)
-        kname = (f"k_generate<{n},{real_t}>" if lanes == 1 else f"k_generate_g<{n},{real_t},{lanes}>")
+        kname = f"k_kin<{n}>+k_rec_g<{n},{real_t},{lanes}>"
     achieved = fp * N / (launch_ms * 1e-3)
     line = {
         "metric": f"events/s at gg->{n - 2}g (n={n}) FP{a.prec} recursion (FP64 kinematics and weights), full generation path",

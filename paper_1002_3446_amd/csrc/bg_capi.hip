@@ -432,7 +432,8 @@ int scale_grid(const bg_config& c, const GenClass& G, ScaleGrid& out) {
 // ----------------------------------------------------------------------------------------
 // Single-class launches.
 // ----------------------------------------------------------------------------------------
-// Staging of the split form: chunks of at most kStageChunk events (at n = 8, 621 MB).
+// Staging of the split forms: chunks of at most kStageChunk events (570 MB at n = 8, 839 MB at
+// n = 12).
 constexpr int64_t kStageChunk = int64_t(1) << 21;
 
 struct ClassPlan {
@@ -450,8 +451,10 @@ int plan_class(const bg_config& c, const GenClass& G, ClassPlan& P) {
                         : (P.wform ? L->generate_w
                                    : (P.lanes == 4 ? L->generate4 : (P.lanes == 2 ? L->generate2 : L->generate)));
   if (!P.fn) return BG_ENOTSUP;
-  P.staged = P.wform || (P.lanes == 1 && split_form(c.n, c.prec));
-  P.block = P.staged ? kLdsLanes : shape_of(c.n, c.prec).block;
+  // staged: the W-tensor form, the table classes, and every grouped form (kinematics in
+  // their own kernel, one lane per event, instead of on every lane of a group)
+  P.staged = P.wform || (P.lanes == 1 && split_form(c.n, c.prec)) || P.lanes > 1;
+  P.block = (P.wform || P.lanes == 1) && P.staged ? kLdsLanes : shape_of(c.n, c.prec).block;
   P.nblocks = (P.lanes * G.count + P.block - 1) / P.block;
   return BG_OK;
 }
@@ -630,7 +633,7 @@ int bg_generate_noalloc(const bg_config* cfg, int64_t count, const bg_inputs* in
     G.pdf.tab = D->ptr + kOffPdf;
   }
   // the staging region holds kNoAllocStage events of n = 8; larger n take shorter chunks
-  const int64_t cap = (int64_t)(kNoAllocStage * split_words(8) / split_words(cfg->n)) / 64 * 64;
+  const int64_t cap = (int64_t)(kNoAllocStage * split_words(8) / split_words(cfg->n)) / 256 * 256;
   GenWork W{out->acc ? D->ptr + kOffParts : nullptr, P.staged ? D->ptr + kOffStage : nullptr,
             P.staged ? cap : 0};
   st = from_hip(P.fn(G, W, P.block, s));
@@ -787,7 +790,7 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   size_t shared_stage = 0;
   for (int k : todo) {
     if (!P[k].staged) continue;
-    scap[k] = std::min<int64_t>(kStageChunk, (G[k].count + kLdsLanes - 1) / kLdsLanes * kLdsLanes);
+    scap[k] = std::min<int64_t>(kStageChunk, (G[k].count + 255) / 256 * 256);  // a multiple of 256
     const size_t sb = (size_t)scap[k] * split_words(cfgs[k].n) * sizeof(double);
     if (concurrent) {
       soff[k] = bytes;

@@ -254,6 +254,62 @@ struct SpanKGroup {
   }
 };
 
+// The same span momenta read from a per-workgroup LDS table filled once per event: for every
+// span of 2..L-1 legs this lane's covariant components, summed left to right in FP64 over
+// its legs and cast to T (bitwise the values SpanKGroup forms at each use), layout
+// [span][component][lane] so that a wave's reads are contiguous.  Single legs and the
+// propagators still come from the FP64 leg momenta.  One table read replaces the FP64 sums
+// and conversions at every use, and nothing of the sums stays live in registers.
+template <int L, int G, typename T>
+struct SpanKGroupLds : SpanKGroup<L, G, T> {
+  using Base = SpanKGroup<L, G, T>;
+  static constexpr int C = Base::C;
+  static constexpr int kSpans = Spans<L>::count - L - 1;  // spans of 2..L-1 legs
+  T* kt;      // &table[0][0][lane]
+  int lanes;  // lanes per workgroup (the table's row stride)
+  __device__ __forceinline__ SpanKGroupLds(const double (&k_)[L][C], const double (&sg_)[C], T* kt_, int lanes_)
+      : Base{k_, sg_}, kt(kt_), lanes(lanes_) {}
+  __device__ __forceinline__ void fill() const {
+    using SP = Spans<L>;
+    static_for<0, L - 1>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      double acc[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = this->k[a][c];
+      static_for<a + 1, L>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += this->k[b][c];
+        if constexpr (b - a + 1 < L) {
+          constexpr int q = SP::at(a, b) - L;
+#pragma unroll
+          for (int c = 0; c < C; ++c) kt[(q * C + c) * lanes] = T(acc[c]);
+        }
+      });
+    });
+    // the recursion reads the table back instead of keeping the values in registers
+    asm volatile("" ::: "memory");
+  }
+  template <int A, int B>
+  __device__ __forceinline__ void K(T (&out)[C]) const {
+    if constexpr (A == B) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[c] = T(this->k[A][c]);
+    } else {
+      constexpr int q = Spans<L>::at(A, B) - L;
+      static_assert(q >= 0 && q < kSpans, "span of 2..L-1 legs");
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[c] = kt[(q * C + c) * lanes];
+    }
+  }
+};
+
+// LDS bytes per lane of SpanKGroupLds
+template <int L, int G, typename T>
+constexpr int span_k_lds_bytes() {
+  return SpanKGroupLds<L, G, T>::kSpans * (4 / G) * (int)sizeof(T);
+}
+
 // One span [A..B]: its bracket sum V (contravariant, this lane's components).
 template <int L, int A, int B, int G, typename T, typename KS, typename SS>
 __device__ __forceinline__ void span_vertex_g(const LaneShare<G, T>& ls, const KS& ks,

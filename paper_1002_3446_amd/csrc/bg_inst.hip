@@ -89,9 +89,7 @@ hipError_t BG_NAME(launch_amp2_w_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const
 #endif
 hipError_t BG_NAME(BG_GEN_GROUP, BG_N, BG_PREC, BG_KIND)(const GenClass& C, const GenWork& W, int block,
                                                          hipStream_t s) {
-  const int64_t nb = (BG_GROUP * C.count + block - 1) / block;
-  hipLaunchKernelGGL((k_generate_g<BG_N, Real, BG_GROUP>), dim3((unsigned)nb), dim3(block), 0, s, C, W.partials);
-  return hipGetLastError();
+  return launch_generate_split_g<BG_N, Real, BG_GROUP>(C, W, block, s);
 }
 #elif BG_KIND == 1 && BG_FORM == 1
 hipError_t BG_NAME(launch_amp2_n, BG_N, BG_PREC, BG_KIND)(int64_t count, const double* mom, const uint32_t* hel,
@@ -112,8 +110,8 @@ hipError_t BG_NAME(BG_AMP2_GROUP, BG_N, BG_PREC, BG_KIND)(int64_t count, const d
                                                           const uint8_t* order, double* out, int block,
                                                           hipStream_t s) {
   const int64_t nb = (BG_GROUP * count + block - 1) / block;
-  hipLaunchKernelGGL((k_amp2_g<BG_N, Real, BG_GROUP>), dim3((unsigned)nb), dim3(block), 0, s, count, mom, hel, order,
-                     out);
+  hipLaunchKernelGGL((k_amp2_g<BG_N, Real, BG_GROUP>), dim3((unsigned)nb), dim3(block),
+                     (grouped_lds_bytes<BG_N, Real, BG_GROUP>(block)), s, count, mom, hel, order, out);
   return hipGetLastError();
 }
 #elif BG_KIND == 2

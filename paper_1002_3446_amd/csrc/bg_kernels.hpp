@@ -501,9 +501,11 @@ __device__ __forceinline__ double ordered_amp2_real(const double (&p)[N][4], con
 }
 
 // The same with the event spread over the G lanes of a group; g is this lane's place in it.
-template <int N, typename T, int G>
+// With ktab (this lane's column of a workgroup table of span_k_lds_bytes per lane, row
+// stride `lanes`), the span momenta come from LDS (SpanKGroupLds), else from registers.
+template <int N, typename T, int G, bool KLDS = false>
 __device__ __forceinline__ double ordered_amp2_g(const double (&p)[N][4], const uint32_t (&leg)[N], uint32_t hel,
-                                                 int g) {
+                                                 int g, T* ktab = nullptr, int lanes = 0) {
   constexpr int C = 4 / G;
   double esum = 0.0;
 #pragma unroll
@@ -534,9 +536,15 @@ __device__ __forceinline__ double ordered_amp2_g(const double (&p)[N][4], const 
       e0.im[c] = ls.pick(e.im, c);
     }
   }
-  SpanKGroup<N - 1, G, T> ks{k, lsd.sg};
   double mr, mi;
-  bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
+  if constexpr (KLDS) {
+    const SpanKGroupLds<N - 1, G, T> ks(k, lsd.sg, ktab, lanes);
+    ks.fill();
+    bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
+  } else {
+    const SpanKGroup<N - 1, G, T> ks{k, lsd.sg};
+    bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
+  }
   return ldexp(__builtin_fma(mr, mr, mi * mi), 2 * ex * (4 - N) - (N - 2));
 }
 
@@ -613,8 +621,9 @@ __device__ __forceinline__ double finish_event(const GenClass& C, int64_t i, boo
 // With G > 1 lanes per event every lane of the group evaluates the kinematics (the same
 // values), the recursion is shared, and lane g = 0 writes the outputs and returns w
 // (the others return 0).  Not used for the table classes, which run split (bg_split.hpp).
-template <int N, typename T, int G = 1, int POL = 0>
-__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, PermLds perm, int g = 0) {
+template <int N, typename T, int G = 1, int POL = 0, bool KLDS = false>
+__device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, PermLds perm, int g = 0,
+                                               T* ktab = nullptr, int lanes = 0) {
   static_assert(POL == 0 || G == 1, "real polarisations run one lane per event");
   using Kin = typename std::conditional<G == 1, EventKin<N>, EventKinPos<N>>::type;
   Kin ev;
@@ -637,7 +646,7 @@ __device__ __forceinline__ double generate_one(const GenClass& C, int64_t i, Per
   } else if constexpr (G == 1) {
     a2 = ordered_amp2<N, T, false>(ev.pc, ev.leg, ev.hel, nullptr);
   } else {
-    a2 = ordered_amp2_g<N, T, G>(ev.pc, ev.leg, ev.hel, g);
+    a2 = ordered_amp2_g<N, T, G, KLDS>(ev.pc, ev.leg, ev.hel, g, ktab, lanes);
   }
   if (g != 0) return 0.0;
   if (C.out.obs) {
@@ -687,23 +696,26 @@ __global__ __launch_bounds__((UseLdsK<N, T>::value ? kLdsLanes : 256)) __attribu
   }
 }
 
-// Single-class generation with G lanes per event (blockDim.x a multiple of 64, at most 256):
-// events blockIdx.x * blockDim.x / G + threadIdx.x / G.
-template <int N, typename T, int G>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_generate_g(GenClass C,
-                                                                                              double* partials) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int g = (int)(threadIdx.x % G);
-  double w = 0.0;
-  if (i < C.count) w = generate_one<N, T, G>(C, i, PermLds{nullptr, 0}, g);
-  if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (int64_t)blockIdx.x);
+// Whether the grouped recursion of precision T reads its span momenta from the LDS table:
+// in FP32 it replaces FP64 sums and conversions at every use; in FP64, whose currents fill
+// the registers, the table's reads add to the scratch spill, so FP64 sums in registers.
+template <typename T>
+constexpr bool span_k_table() {
+  return sizeof(T) == 4;
 }
 
-// bg_amp2 with G lanes per event.
+// Dynamic LDS of the grouped kernels for workgroups of `block` lanes: the span-momentum table
+template <int N, typename T, int G>
+constexpr int grouped_lds_bytes(int block) {
+  return span_k_table<T>() ? span_k_lds_bytes<N - 1, G, T>() * block : 0;
+}
+
+// bg_amp2 with G lanes per event.  Dynamic LDS: grouped_lds_bytes.
 template <int N, typename T, int G>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_amp2_g(
     int64_t count, const double* __restrict__ mom, const uint32_t* __restrict__ hel, const uint8_t* __restrict__ order,
     double* __restrict__ out) {
+  extern __shared__ unsigned char gdyn[];
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int g = (int)(threadIdx.x % G);
   if (i >= count) return;
@@ -717,7 +729,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) p[t][mu] = q[mu];
   }
-  const double a2 = ordered_amp2_g<N, T, G>(p, leg, hel[i], g);
+  const double a2 = ordered_amp2_g<N, T, G, span_k_table<T>()>(p, leg, hel[i], g,
+                                                               reinterpret_cast<T*>(gdyn) + threadIdx.x,
+                                                               (int)blockDim.x);
   if (g == 0) out[i] = a2;
 }
 

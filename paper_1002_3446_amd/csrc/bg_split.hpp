@@ -100,6 +100,35 @@ __device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t 
   return finish_event<N>(C, i, pass, a2, shat, x1, x2, r);
 }
 
+// The same with the event on the G lanes of a group (the grouped recursion; span momenta
+// from this lane's column ktab of the workgroup's LDS table where span_k_table); lane g = 0
+// writes the outputs and returns w, the others return 0.
+template <int N, typename T, int G>
+__device__ __forceinline__ double rec_one_g(const GenClass& C, int64_t i, int64_t j, const double* __restrict__ buf,
+                                            int g, T* ktab, int lanes) {
+  using L = SplitLayout<N>;
+  const double shat = buf[L::at(j, L::kShat)];
+  double pc[N][4];
+  const double hb = 0.5 * (C.use_pdf ? sqrt(shat) : C.sqrt_s);
+  pc[0][0] = hb;
+  pc[0][1] = 0.0;
+  pc[0][2] = 0.0;
+  pc[0][3] = hb;
+#pragma unroll
+  for (int t = 1; t < N; ++t)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) pc[t][mu] = buf[L::at(j, L::kMom + 4 * (t - 1) + mu)];
+  const uint64_t meta = (uint64_t)__double_as_longlong(buf[L::at(j, L::kMeta)]);
+  const uint64_t legs = (uint64_t)__double_as_longlong(buf[L::at(j, L::kLegs)]);
+  uint32_t leg[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) leg[t] = (uint32_t)(legs >> (4 * t)) & 15u;
+  const double a2 = ordered_amp2_g<N, T, G, span_k_table<T>()>(pc, leg, (uint32_t)meta, g, ktab, lanes);
+  if (g != 0) return 0.0;
+  const bool pass = ((meta >> 32) & 1u) != 0;
+  return finish_event<N>(C, i, pass, a2, shat, buf[L::at(j, L::kX1)], buf[L::at(j, L::kX2)], buf[L::at(j, L::kR)]);
+}
+
 // Launch: blockDim.x = kKinBlock, perm_lds_bytes(N, kKinBlock) bytes of dynamic LDS,
 // ceil(cnt / kKinBlock) workgroups; events first .. first + cnt - 1 into slots 0 .. cnt - 1.
 template <int N>
@@ -119,6 +148,44 @@ __global__ __launch_bounds__(kLdsLanes) __attribute__((amdgpu_waves_per_eu(1, 1)
   double w = 0.0;
   if (j < cnt) w = rec_one<N, POL>(C, first + j, j, buf, &tab);
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (first / kLdsLanes + (int64_t)blockIdx.x));
+}
+
+// Launch: blockDim.x a multiple of 64 (at most 256), ceil(cnt G / blockDim.x) workgroups,
+// grouped_lds_bytes<N, T, G>(blockDim.x) bytes of dynamic LDS, first a multiple of
+// blockDim.x / G; workgroup b writes the partial of its blockDim.x / G events at
+// first G / blockDim.x + b, as the one-kernel form numbers them.
+template <int N, typename T, int G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rec_g(
+    GenClass C, int64_t first, int64_t cnt, const double* __restrict__ buf, double* partials) {
+  extern __shared__ unsigned char gdyn[];
+  const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int g = (int)(threadIdx.x % G);
+  double w = 0.0;
+  if (j < cnt) w = rec_one_g<N, T, G>(C, first + j, j, buf, g, reinterpret_cast<T*>(gdyn) + threadIdx.x, (int)blockDim.x);
+  if (partials)
+    block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0},
+                       partials + 4 * (first * G / (int64_t)blockDim.x + (int64_t)blockIdx.x));
+}
+
+// The kinematics kernel and the grouped recursion kernel over the class in chunks of
+// W.stage_cap events (a multiple of 256); workgroups of `block` lanes.
+template <int N, typename T, int G>
+hipError_t launch_generate_split_g(const GenClass& C, const GenWork& W, int block, hipStream_t s) {
+  if (C.count <= 0) return hipSuccess;
+  if (!W.stage || W.stage_cap < 256 || W.stage_cap % 256 != 0 || block % 64 != 0 || block > 256)
+    return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  for (int64_t first = 0; first < C.count && e == hipSuccess; first += W.stage_cap) {
+    const int64_t cnt = std::min<int64_t>(W.stage_cap, C.count - first);
+    hipLaunchKernelGGL((k_kin<N>), dim3((unsigned)((cnt + kKinBlock - 1) / kKinBlock)), dim3(kKinBlock),
+                       perm_lds_bytes(N, kKinBlock), s, C, first, cnt, W.stage);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL((k_rec_g<N, T, G>), dim3((unsigned)((cnt * G + block - 1) / block)), dim3(block),
+                       (grouped_lds_bytes<N, T, G>(block)), s, C, first, cnt, W.stage, W.partials);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 // Both kernels over the class in chunks of W.stage_cap events (a multiple of 64) through the
