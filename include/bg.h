@@ -117,11 +117,13 @@ typedef struct {
                         function, no sampling density); -inf when |A|^2 = 0 */
 } bg_outputs;
 
-/* Generate events of ncfg classes (Sec. 3).  One class: FP32 classes with n <= 8 run as a
- * kinematics kernel and a recursion kernel joined by a staging buffer ((4n + 2) * 8 B per
- * event, chunks of at most 2^21 events); the others as one kernel per call (after a small
- * setup launch, once per density and device, that tabulates the inverse CDF of the parton
- * density when x1, x2 are sampled).  Several classes (mixed multiplicities): as chosen by
+/* Generate events of ncfg classes (Sec. 3).  One class: a kinematics kernel (one lane per
+ * event) and a recursion kernel joined by a staging buffer ((4n + 2) * 8 B per event, chunks
+ * of at most 2^21 events), for FP32 n <= 8 and every form with two or four lanes per event
+ * or the W-tensor form; the one-lane classes without the LDS span table (FP32 n = 9 with one
+ * lane, FP64 n <= 6) and real polarisations beyond FP32 n = 8 as one kernel.  A small setup
+ * launch, once per density and device, tabulates the inverse CDF of the parton density when
+ * x1, x2 are sampled.  Several classes (mixed multiplicities): as chosen by
  * bg_set_mixed_launch, either one after another, or the FP32 classes in one persistent
  * launch whose workgroups take tiles (largest n first) from a shared queue, or side by side
  * on concurrent streams.  Class k gets counts[k] events with indices
@@ -146,9 +148,11 @@ int bg_generate(const bg_config *cfgs, int ncfg, const int64_t *counts,
  * own.  Every buffer the call needs lives in a library array that each GPU holds from the
  * first such call until the process ends (about 27 MiB): the inverse-CDF table of the
  * density last used (rebuilt by a small kernel when the density changes), the partials of
- * the compensated sums and the split form's staging (chunks of 2^16 events).  The kernels,
+ * the compensated sums and the split form's staging (chunks of 2^16 events at n = 8, fewer
+ * at larger n).  The kernels,
  * the partial layout and their reduction are bg_generate's, so every per-event output and
- * the totals equal bg_generate's bitwise.  count <= 2^24 (else BG_EINVAL).  All calls on
+ * the totals equal bg_generate's bitwise.  count <= 2^24 and at most 2^18 + 1 workgroups
+ * (count x lanes per event / workgroup size), else BG_EINVAL.  All calls on
  * one GPU share that array and it keeps the last call's contents: calls that overlap on one
  * GPU (other streams, other threads) race; order them.  Errors as bg_generate. */
 int bg_generate_noalloc(const bg_config *cfg, int64_t count, const bg_inputs *in, const bg_outputs *out,
@@ -176,8 +180,8 @@ int bg_amp2(int n, int prec, int64_t N, const double *mom, const uint32_t *hel,
  * Events with |A|^2 = 0 or not finite (non-finite inputs) get log w = -inf and zero
  * gradients.
  * Supported for n = 4..12 in both precisions.  The recursion's reverse sweep runs one lane
- * per event for FP32 n <= 5 and FP64 n = 4, else four lanes per event (each holding one
- * Lorentz component of every current and of its adjoint).  BG_ENOTSUP for real
+ * per event for FP32 n <= 5 and FP64 n = 4, two lanes for FP32 n = 6..8 and FP64 n = 5, 6,
+ * else four (a lane holds 4 / lanes Lorentz components of every current and its adjoint).  BG_ENOTSUP for real
  * polarisations and the dynamic scale. */
 int bg_amp2_grad(const bg_config *cfg, int64_t N, const double *uniforms, const double *x12,
                  const uint32_t *hel, const uint8_t *order, const double *gout,

@@ -559,20 +559,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   for (int t = 1; t < N; ++t) {
     const double sg = K.leg[t] < 2u ? -K.sc : K.sc;
 #pragma unroll
-    for (int c = 0; c < C; ++c) k[t - 1][c] = lsd.sg[c] * (sg * lsd.pick(K.pc[t], c));
+    for (int c = 0; c < C; ++c) k[t - 1][c] = lsd.sg[c] * (sg * lsd.template pick<true>(K.pc[t], c));
     const cv4<T> e = polarisation<T>(K.pc[t], (K.hel >> K.leg[t]) & 1u);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      src[t - 1].re[c] = ls.pick(e.re, c);
-      src[t - 1].im[c] = ls.pick(e.im, c);
+      src[t - 1].re[c] = ls.template pick<true>(e.re, c);
+      src[t - 1].im[c] = ls.template pick<true>(e.im, c);
     }
   }
   {
     const cv4<T> e = polarisation<T>(K.pc[0], K.hel & 1u);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      e0.re[c] = ls.pick(e.re, c);
-      e0.im[c] = ls.pick(e.im, c);
+      e0.re[c] = ls.template pick<true>(e.re, c);
+      e0.im[c] = ls.template pick<true>(e.im, c);
     }
   }
   SpanKGroup<L, GL, T, true> ks{k, lsd.sg};

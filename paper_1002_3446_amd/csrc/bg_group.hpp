@@ -63,15 +63,16 @@ struct LaneShare {
     for (int c = 0; c < C; ++c) sg[c] = (mu0 + c == 0) ? T(1) : T(-1);
   }
   // the held components of a full four-vector, without dynamic register indexing: one select
-  // for two lanes; for four, bit masks (a chain of three selects is turned back into a
-  // dynamically indexed array on the stack)
-  template <typename U>
+  // for two lanes in the forward kernels; bit masks for four lanes, and for two in the
+  // gradient kernels (BITS), where selects between elements of one array are turned back into
+  // a dynamically indexed array on the stack
+  template <bool BITS = false, typename U>
   __device__ __forceinline__ U pick(const U (&v)[4], int c) const {
-    if constexpr (G == 4) {
+    if constexpr (G == 4 || BITS) {
       using B = typename std::conditional<sizeof(U) == 8, uint64_t, uint32_t>::type;
       B r = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) r |= __builtin_bit_cast(B, v[q]) & (B)(-(B)(mu0 == q));
+      for (int q = 0; q < G; ++q) r |= __builtin_bit_cast(B, v[q * C + c]) & (B)(-(B)(mu0 == q * C));
       return __builtin_bit_cast(U, r);
     } else {
       U r = v[c];

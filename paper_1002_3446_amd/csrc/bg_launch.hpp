@@ -43,13 +43,14 @@ constexpr bool has_real_pol(int n, int prec) { return prec == 32 ? n <= 12 : n <
 // large n chosen per class (bg_set_form); FP64 at n = 6 and 10 for parity with the oracle.
 constexpr bool has_wtensor(int n, int prec) { return prec == 32 ? (n == 8 || n >= 10) : (n == 6 || n == 10); }
 
-// The gradient kernel with an event on two lanes (forward values staged in LDS, which
-// bounds it to FP32 n <= 8); elsewhere one lane per event.
 // Lanes per event of the gradient's recursion kernel: one (k_grad) for FP32 n <= 5 and
-// FP64 n = 4, else the grouped reverse sweep (k_grad_g) with four lanes, one Lorentz
-// component each: the currents and their adjoints stay in registers through FP32 n = 11
-// and FP64 n = 9.
-constexpr int grad_lanes(int n, int prec) { return prec == 32 ? (n <= 5 ? 1 : 4) : (n <= 4 ? 1 : 4); }
+// FP64 n = 4; else the grouped reverse sweep (k_grad_g), with two lanes (two Lorentz
+// components each) while the currents and their adjoints fit a lane's registers (FP32
+// n = 6..8, FP64 n = 5, 6: fewer cross-lane sums, and the kinematics on half as many lanes),
+// and four lanes beyond (no scratch through FP32 n = 11 and FP64 n = 8).
+constexpr int grad_lanes(int n, int prec) {
+  return prec == 32 ? (n <= 5 ? 1 : (n <= 8 ? 2 : 4)) : (n <= 4 ? 1 : (n <= 6 ? 2 : 4));
+}
 
 struct GradArgs {
   int64_t count;
