@@ -215,8 +215,9 @@ struct SpanKGroup {
   const double (&sg)[C];     // their metric signs
   // With AFRESH, every use sums afresh: an optimisation barrier on the first term keeps the
   // compiler from merging the sums of one span over the whole kernel and holding them in
-  // registers (the gradient kernels, which hold currents and adjoints, gain registers; the
-  // forward kernels lose more to the extra FP64 adds than they gain).
+  // registers (the gradient kernels, which hold currents and adjoints, and the FP64 forward
+  // forms that would otherwise spill gain registers; elsewhere the forward kernels lose more
+  // to the extra FP64 adds than they gain).
   template <int A, int B>
   __device__ __forceinline__ void sum(double d[C]) const {
 #pragma unroll

@@ -503,6 +503,13 @@ __device__ __forceinline__ double ordered_amp2_real(const double (&p)[N][4], con
 // The same with the event spread over the G lanes of a group; g is this lane's place in it.
 // With ktab (this lane's column of a workgroup table of span_k_lds_bytes per lane, row
 // stride `lanes`), the span momenta come from LDS (SpanKGroupLds), else from registers.
+// Whether the grouped forward recursion forms each span momentum afresh at every use (FP64
+// with two lanes from n = 9, with four from n = 11): keeping every span's sums live would
+// spill there (n = 12, four lanes: 656 against 400 B of scratch per lane; n = 9, two lanes:
+// 512 against 288 B), and the extra FP64 additions cost less than the spill traffic.
+template <int N, typename T, int G>
+constexpr bool fwd_afresh() { return std::is_same<T, double>::value && (N >= 11 || (G == 2 && N >= 9)); }
+
 template <int N, typename T, int G, bool KLDS = false>
 __device__ __forceinline__ double ordered_amp2_g(const double (&p)[N][4], const uint32_t (&leg)[N], uint32_t hel,
                                                  int g, T* ktab = nullptr, int lanes = 0) {
@@ -542,7 +549,7 @@ __device__ __forceinline__ double ordered_amp2_g(const double (&p)[N][4], const 
     ks.fill();
     bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
   } else {
-    const SpanKGroup<N - 1, G, T> ks{k, lsd.sg};
+    const SpanKGroup<N - 1, G, T, fwd_afresh<N, T, G>()> ks{k, lsd.sg};
     bg_amplitude_g<N - 1, G, T>(ls, ks, src, e0, mr, mi);
   }
   return ldexp(__builtin_fma(mr, mr, mi * mi), 2 * ex * (4 - N) - (N - 2));
