@@ -117,11 +117,8 @@ hipError_t BG_NAME(BG_AMP2_GROUP, BG_N, BG_PREC, BG_KIND)(int64_t count, const d
 #elif BG_KIND == 2
 // Two kernels: the recursion and its reverse sweep (one, two or four lanes per event), then
 // the helicity-source, momentum, RAMBO and x adjoints (one lane per event).
-#ifndef BG_GRAD_LANES
-#define BG_GRAD_LANES grad_lanes(BG_N, BG_PREC)
-#endif
 hipError_t BG_NAME(launch_grad_n, BG_N, BG_PREC, BG_KIND)(const GradArgs& G, int block, hipStream_t s) {
-  constexpr int GL = BG_GRAD_LANES;
+  constexpr int GL = grad_lanes(BG_N, BG_PREC);
   if constexpr (GL == 1) {
     const int64_t nb = (G.count + block - 1) / block;
     hipLaunchKernelGGL((k_grad<BG_N, Real>), dim3((unsigned)nb), dim3(block), 0, s, G);

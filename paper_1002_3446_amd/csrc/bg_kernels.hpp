@@ -168,16 +168,16 @@ __device__ __forceinline__ void build_event(const GenClass& C, int64_t i, EventK
   }
 }
 
-// eta = asinh(pz / pT) of a momentum with transverse momentum pT, as sign(pz) log((|p| + |pz|)
-// / pT): the same function, since (|p| + |pz|)(|p| - |pz|) = pT^2.  Every step is a sum of
-// positive terms, a division or the logarithm, so the absolute error is a few units of
-// 2^-53 |eta| (the cuts and Delta R only use eta through |eta| and differences); pT = 0
-// gives +-inf.
-__device__ __forceinline__ double pseudorapidity(double pt, double pz) {
+// eta = asinh(pz / pT) of a massless momentum with energy E and transverse momentum pT, as
+// sign(pz) log((E + |pz|) / pT): the same function, since (|p| + |pz|)(|p| - |pz|) = pT^2
+// and |p| = E.  E stands in for |p| (the momenta are massless up to rounding, so they agree
+// to a few units of 2^-53), which saves the square root.  Every step is a sum of positive
+// terms, a division or the logarithm, so the absolute error is a few units of 2^-53 |eta|
+// (the cuts and Delta R only use eta through |eta| and differences); pT = 0 gives +-inf.
+__device__ __forceinline__ double pseudorapidity(double pt, double pz, double e) {
 #pragma clang fp contract(off)
   const double az = fabs(pz);
-  const double pabs = sqrt(pt * pt + az * az);
-  return copysign(log_fp64((pabs + az) / pt), pz);
+  return copysign(log_fp64((e + az) / pt), pz);
 }
 
 // Jet cuts and observables (Sec. 3, Sec. 4) on the outgoing legs (lab frame).  H_T is summed
@@ -194,7 +194,7 @@ __device__ __forceinline__ bool cuts(const GenClass& C, const EventKin<N>& ev, P
   for (int p = 0; p < NF; ++p) {
     const double* m = ev.pl[p];
     pt[p] = sqrt(m[1] * m[1] + m[2] * m[2]);
-    eta[p] = pseudorapidity(pt[p], m[3]);
+    eta[p] = pseudorapidity(pt[p], m[3], m[0]);
     phi[p] = atan2(m[2], m[1]);
     perm.col[p * perm.stride] = pt[p];
     ok = ok && (pt[p] > C.pt_min) && (fabs(eta[p]) < C.eta_max);
@@ -361,7 +361,7 @@ __device__ __forceinline__ bool cuts_positions(const GenClass& C, const EventKin
   for (int t = 1; t < N; ++t) {
     const double* p = ev.p[t];
     pt[t] = sqrt(p[1] * p[1] + p[2] * p[2]);
-    eta[t] = pseudorapidity(pt[t], p[3]);
+    eta[t] = pseudorapidity(pt[t], p[3], p[0]);
     phi[t] = atan2(p[2], p[1]);
     const bool out = ev.leg[t] >= 2u;
     if (out) {
