@@ -437,7 +437,7 @@ def main():
     launch_ms = sum(ms) / len(ms)
     fp = flops_plain(n)
     fe = flops_executed(n)
-    # FP32 n <= 8 runs as a kinematics and a recursion kernel per chunk of 2^21 events: the
+    # FP32 n <= 8 runs as a kinematics and a recursion kernel per chunk of 2^22 events: the
     # timed unit is then the whole bg_generate call (both kernels, every chunk)
     real_t = "float" if a.prec == 32 else "double"
     peak = PEAK_FP32 if a.prec == 32 else PEAK_FP64

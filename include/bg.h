@@ -119,7 +119,7 @@ typedef struct {
 
 /* Generate events of ncfg classes (Sec. 3).  One class: a kinematics kernel (one lane per
  * event) and a recursion kernel joined by a staging buffer ((4n + 2) * 8 B per event, chunks
- * of at most 2^21 events), for FP32 n <= 8 and every form with two or four lanes per event
+ * of at most 2^22 events), for FP32 n <= 8 and every form with two or four lanes per event
  * or the W-tensor form; the one-lane classes without the LDS span table (FP32 n = 9 with one
  * lane, FP64 n <= 6) and real polarisations beyond FP32 n = 8 as one kernel.  A small setup
  * launch, once per density and device, tabulates the inverse CDF of the parton density when

@@ -432,9 +432,13 @@ int scale_grid(const bg_config& c, const GenClass& G, ScaleGrid& out) {
 // ----------------------------------------------------------------------------------------
 // Single-class launches.
 // ----------------------------------------------------------------------------------------
-// Staging of the split forms: chunks of at most kStageChunk events (570 MB at n = 8, 839 MB at
-// n = 12).
-constexpr int64_t kStageChunk = int64_t(1) << 21;
+// Staging of the split forms: chunks of at most kStageChunk events (1.14 GB at n = 8, 1.68 GB
+// at n = 12).  Every chunk costs two kernel boundaries, at which the GPU drains (the last
+// workgroups of one kernel finish unevenly before the next kernel starts), so fewer, larger
+// chunks waste less, up to the memory pool's 4 GiB release threshold (n = 8 FP32, 2^24
+// events: 6.78 ms in chunks of 2^21, 6.59 ms in chunks of 2^22, 6.63 ms in 2^23, 6.76 ms in
+// one chunk of 4.6 GB).
+constexpr int64_t kStageChunk = int64_t(1) << 22;
 
 struct ClassPlan {
   int lanes, block;
