@@ -290,7 +290,8 @@ const char *bg_strerror(int status);
 int bg_version(void);
 
 /* Identity of the sources the library was built from: the first 16 hexadecimal digits of a
- * sha256 over the kernel sources and this header (static string). */
+ * sha256 over the kernel sources, this header and the build script with its compiler flags
+ * (static string). */
 const char *bg_source_hash(void);
 
 #ifdef __cplusplus

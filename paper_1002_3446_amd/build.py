@@ -33,14 +33,16 @@ FLAGS = [
 
 
 def source_hash() -> str:
-    """sha256 (first 16 hex digits) over the kernel sources in csrc/ (sorted by name) and the
-    C header: the identity a built library carries and the binding checks."""
+    """sha256 (first 16 hex digits) over the kernel sources in csrc/ (sorted by name), the
+    C header and this file (the compiler flags of every unit): the identity a built library
+    carries and the binding checks."""
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
         if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
             h.update(open(os.path.join(CSRC, f), "rb").read())
     h.update(open(HEADER, "rb").read())
+    h.update(open(os.path.abspath(__file__), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -76,6 +78,20 @@ def has_wtensor(n: int, p: int) -> bool:
     return (n == 8 or n >= 10) if p == 32 else n in (6, 10)
 
 
+def unit_flags(n: int, p: int, k: int, f: int) -> list[str]:
+    """Extra compiler flags of one kernel unit.  The generation and bg_amp2 units of FP32 n = 8
+    (one lane) and of FP64 n >= 8 (two or four lanes) are built without LLVM's pre-RA machine
+    scheduler: there the recursion fills the register file at one wave per SIMD, and the
+    scheduler's reordering for latency raises register pressure, which costs more (scratch
+    spill, AGPR copies) than the latency it hides.  Measured on generation, alternating runs
+    on one GPU: FP32 n = 8 6.69 -> 6.53-6.61 ms per 2^24 events; FP64 n = 8 11.1 -> 11.0 ms per
+    2^24, n = 9 5.23 -> 5.01, n = 10 unchanged, n = 11 12.99 -> 12.71, n = 12 20.57 -> 18.45 ms
+    per 2^22 (scratch 400 -> 248 B per lane).  FP32 n = 12 lost 0.8% without it and keeps it."""
+    if k < 2 and ((p == 32 and f == 1 and n == 8) or (p == 64 and f in (2, 5) and n >= 8)):
+        return ["-mllvm", "-enable-misched=0"]
+    return []
+
+
 def units_for(ns, precs=(32, 64), kinds=KINDS):
     """(source, object, defines, expected cost) of every unit; the costliest start first."""
     units = [(os.path.join(CSRC, "bg_capi.hip"), os.path.join(OUT_DIR, "bg_capi.o"),
@@ -99,7 +115,8 @@ def units_for(ns, precs=(32, 64), kinds=KINDS):
                     obj = os.path.join(OUT_DIR, f"bg_n{n:02d}_p{p}_k{k}_f{f}.o")
                     cost = n ** 3 * (2 if p == 64 else 1) * (4 if k == 2 else 1)
                     units.append((os.path.join(CSRC, "bg_inst.hip"), obj,
-                                  [f"-DBG_N={n}", f"-DBG_PREC={p}", f"-DBG_KIND={k}", f"-DBG_FORM={f}"], cost))
+                                  [f"-DBG_N={n}", f"-DBG_PREC={p}", f"-DBG_KIND={k}", f"-DBG_FORM={f}"]
+                                  + unit_flags(n, p, k, f), cost))
     units.sort(key=lambda u: -u[3])
     return units
 
