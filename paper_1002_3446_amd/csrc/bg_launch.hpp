@@ -76,6 +76,8 @@ struct GenWork {
   double* partials;
   double* stage;
   int64_t stage_cap;
+  int64_t ahead;  // one-lane recursion kernel: tiles between a workgroup and the tile whose
+                  // staged words it pulls into the L2 cache for a later workgroup (0: none)
 };
 
 using GenerateFn = hipError_t (*)(const GenClass& C, const GenWork& W, int block, hipStream_t s);

@@ -60,17 +60,36 @@ __device__ __forceinline__ void kin_one(const GenClass& C, int64_t i, int64_t j,
   buf[L::at(j, L::kLegs)] = __longlong_as_double((long long)legs);
 }
 
-// |A|^2, weight and outputs of event i from staging slot j (one lane per event, the span
-// table in tab); returns w.  Every lane of the wave must call it (the table fill is
-// preceded by a workgroup barrier).
-template <int N, int POL = 0>
-__device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t j, const double* __restrict__ buf,
-                                          LdsTable<N>* tab) {
+// One event's staged words in registers.
+template <int N>
+struct Staged {
+  double pc[N - 1][4];  // positions 1..N-1
+  double shat, x1, x2, r;
+  uint64_t meta, legs;
+};
+
+template <int N>
+__device__ __forceinline__ void load_staged(const double* __restrict__ buf, int64_t j, Staged<N>& s) {
   using L = SplitLayout<N>;
-  const double shat = buf[L::at(j, L::kShat)];
+#pragma unroll
+  for (int t = 1; t < N; ++t)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) s.pc[t - 1][mu] = buf[L::at(j, L::kMom + 4 * (t - 1) + mu)];
+  s.shat = buf[L::at(j, L::kShat)];
+  s.x1 = buf[L::at(j, L::kX1)];
+  s.x2 = buf[L::at(j, L::kX2)];
+  s.r = buf[L::at(j, L::kR)];
+  s.meta = (uint64_t)__double_as_longlong(buf[L::at(j, L::kMeta)]);
+  s.legs = (uint64_t)__double_as_longlong(buf[L::at(j, L::kLegs)]);
+}
+
+// |A|^2, weight and outputs of event i from its staged words (one lane per event, the span
+// table in tab); returns w.
+template <int N, int POL = 0>
+__device__ __forceinline__ double rec_staged(const GenClass& C, int64_t i, const Staged<N>& s, LdsTable<N>* tab) {
   double pc[N][4];
   // position 0: the beam leg 0, as build_event forms it
-  const double hb = 0.5 * (C.use_pdf ? sqrt(shat) : C.sqrt_s);
+  const double hb = 0.5 * (C.use_pdf ? sqrt(s.shat) : C.sqrt_s);
   pc[0][0] = hb;
   pc[0][1] = 0.0;
   pc[0][2] = 0.0;
@@ -78,17 +97,12 @@ __device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t 
 #pragma unroll
   for (int t = 1; t < N; ++t)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) pc[t][mu] = buf[L::at(j, L::kMom + 4 * (t - 1) + mu)];
-  const double x1 = buf[L::at(j, L::kX1)];
-  const double x2 = buf[L::at(j, L::kX2)];
-  const double r = buf[L::at(j, L::kR)];
-  const uint64_t meta = (uint64_t)__double_as_longlong(buf[L::at(j, L::kMeta)]);
-  const uint64_t legs = (uint64_t)__double_as_longlong(buf[L::at(j, L::kLegs)]);
+    for (int mu = 0; mu < 4; ++mu) pc[t][mu] = s.pc[t - 1][mu];
   uint32_t leg[N];
 #pragma unroll
-  for (int t = 0; t < N; ++t) leg[t] = (uint32_t)(legs >> (4 * t)) & 15u;
-  const uint32_t hel = (uint32_t)meta;
-  const bool pass = ((meta >> 32) & 1u) != 0;
+  for (int t = 0; t < N; ++t) leg[t] = (uint32_t)(s.legs >> (4 * t)) & 15u;
+  const uint32_t hel = (uint32_t)s.meta;
+  const bool pass = ((s.meta >> 32) & 1u) != 0;
   double a2;
   if constexpr (POL == 1) {
     double cs[N][2];
@@ -97,7 +111,16 @@ __device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t 
   } else {
     a2 = ordered_amp2<N, float, true>(pc, leg, hel, tab);
   }
-  return finish_event<N>(C, i, pass, a2, shat, x1, x2, r);
+  return finish_event<N>(C, i, pass, a2, s.shat, s.x1, s.x2, s.r);
+}
+
+// The same from staging slot j.
+template <int N, int POL = 0>
+__device__ __forceinline__ double rec_one(const GenClass& C, int64_t i, int64_t j, const double* __restrict__ buf,
+                                          LdsTable<N>* tab) {
+  Staged<N> s;
+  load_staged<N>(buf, j, s);
+  return rec_staged<N, POL>(C, i, s, tab);
 }
 
 // The same with the event on the G lanes of a group (the grouped recursion; span momenta
@@ -140,13 +163,34 @@ __global__ __launch_bounds__(kKinBlock) void k_kin(GenClass C, int64_t first, in
 
 // Launch: blockDim.x = kLdsLanes, ceil(cnt / kLdsLanes) workgroups, first a multiple of
 // kLdsLanes; workgroup b writes the partial of events first + 64 b .. (partial first / 64 + b).
+// With ahead > 0 the workgroup, after issuing its own loads, pulls the staged words of tile
+// blockIdx.x + ahead into the L2 cache (one 4-byte load per 128-byte line, written to a
+// 256-byte LDS scrap area and never read): with ahead the number of workgroups resident at
+// once (one per SIMD), that tile is the one started on the same XCD about a workgroup's
+// duration later, whose first loads then hit L2 instead of HBM.
 template <int N, int POL>
 __global__ __launch_bounds__(kLdsLanes) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rec(
-    GenClass C, int64_t first, int64_t cnt, const double* __restrict__ buf, double* partials) {
+    GenClass C, int64_t first, int64_t cnt, const double* __restrict__ buf, double* partials, int64_t ahead) {
   __shared__ LdsTable<N> tab;
+  __shared__ unsigned int scrap[kLdsLanes];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Staged<N> st;
+  if (j < cnt) load_staged<N>(buf, j, st);
+  const int64_t t = (int64_t)blockIdx.x + ahead;
+  if (ahead > 0 && t * kLdsLanes < cnt) {
+    // the tile's words are contiguous (SplitLayout): kWords x 64 doubles
+    constexpr int kBytes = SplitLayout<N>::kWords * kLdsLanes * 8;
+    const char* base = reinterpret_cast<const char*>(buf + t * kLdsLanes * SplitLayout<N>::kWords);
+#pragma unroll
+    for (int off = 0; off < kBytes; off += kLdsLanes * 128) {
+      const int o = off + (int)threadIdx.x * 128;
+      if (o < kBytes)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(base + o),
+                                         (__attribute__((address_space(3))) void*)scrap, 4, 0, 0);
+    }
+  }
   double w = 0.0;
-  if (j < cnt) w = rec_one<N, POL>(C, first + j, j, buf, &tab);
+  if (j < cnt) w = rec_staged<N, POL>(C, first + j, st, &tab);
   if (partials) block_reduce_store(CSum{w, 0.0}, CSum{w * w, 0.0}, partials + 4 * (first / kLdsLanes + (int64_t)blockIdx.x));
 }
 
@@ -202,7 +246,7 @@ hipError_t launch_generate_split(const GenClass& C, const GenWork& W, hipStream_
     e = hipGetLastError();
     if (e != hipSuccess) break;
     hipLaunchKernelGGL((k_rec<N, POL>), dim3((unsigned)((cnt + kLdsLanes - 1) / kLdsLanes)), dim3(kLdsLanes), 0, s, C,
-                       first, cnt, W.stage, W.partials);
+                       first, cnt, W.stage, W.partials, W.ahead);
     e = hipGetLastError();
   }
   return e;
