@@ -808,9 +808,12 @@ int bg_generate(const bg_config* cfgs, int ncfg, const int64_t* counts, const bg
   bytes += shared_stage;
   Workspace ws{nullptr, s};
   if (int st = ws_alloc(&ws.p, bytes, s); st != BG_OK) return st;
+  // the one-lane recursion prefetches the tile half a resident round ahead (two workgroups per
+  // CU): a full round ahead, more than half of the prefetched lines left L2 before their use
+  // (the recursion kernel read 58% more from HBM, for the same time)
   auto run_class = [&](int k, hipStream_t t) {
     GenWork W{outs[k].acc ? ws.d() + off[k] / sizeof(double) : nullptr,
-              scap[k] > 0 ? ws.d() + soff[k] / sizeof(double) : nullptr, scap[k], (int64_t)cu_count() * 4};
+              scap[k] > 0 ? ws.d() + soff[k] / sizeof(double) : nullptr, scap[k], (int64_t)cu_count() * 2};
     int st = from_hip(P[k].fn(G[k], W, P[k].block, t));
     if (st == BG_OK && W.partials)
       st = from_hip(launch_finalize(W.partials, P[k].nblocks, W.partials + 4 * P[k].nblocks, outs[k].acc, t));

@@ -165,9 +165,10 @@ __global__ __launch_bounds__(kKinBlock) void k_kin(GenClass C, int64_t first, in
 // kLdsLanes; workgroup b writes the partial of events first + 64 b .. (partial first / 64 + b).
 // With ahead > 0 the workgroup, after issuing its own loads, pulls the staged words of tile
 // blockIdx.x + ahead into the L2 cache (one 4-byte load per 128-byte line, written to a
-// 256-byte LDS scrap area and never read): with ahead the number of workgroups resident at
-// once (one per SIMD), that tile is the one started on the same XCD about a workgroup's
-// duration later, whose first loads then hit L2 instead of HBM.
+// 256-byte LDS scrap area and never read).  Workgroups go to the XCDs in turn and one runs
+// per SIMD, so with ahead a multiple of 8 and below the number resident at once, that tile
+// starts on the same XCD a fraction of a workgroup's duration later and its first loads hit
+// L2 instead of HBM.
 template <int N, int POL>
 __global__ __launch_bounds__(kLdsLanes) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rec(
     GenClass C, int64_t first, int64_t cnt, const double* __restrict__ buf, double* partials, int64_t ahead) {
